@@ -1,0 +1,411 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-type the oracle's formulas: each checks it against a closed form, an
+invariance, an independent solver (SciPy), finite differences, brute-force NumPy, or
+values the paper prints.  A plausible slip in the oracle (a dropped term, a flipped
+sign, a transposed index) breaks at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import least_squares
+from scipy.spatial.transform import Rotation
+
+import oracle
+from paper_1707_00385_amd import scenes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _frame_with_z(z, theta):
+    """Rotation whose third column is the unit vector z, rotated in-plane by theta."""
+    z = np.asarray(z, dtype=float)
+    z = z / np.linalg.norm(z)
+    a = np.array([0.0, 1.0, 0.0]) if abs(z[1]) < 0.9 else np.array([1.0, 0.0, 0.0])
+    x = np.cross(a, z)
+    x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    xr = math.cos(theta) * x + math.sin(theta) * y
+    yr = np.cross(z, xr)
+    return np.stack([xr, yr, z], axis=1)
+
+
+def _cam(sc):
+    c = sc.camera
+    return c.fx, c.fy, c.cx, c.cy
+
+
+# --------------------------------------------------------------------------- model pins
+
+def test_jacobian_matches_finite_differences():
+    """J of Section 3.2.3: derivatives w.r.t. small rotations about the current local
+    x and y axes, t_z, A, B, C, checked by central differences of the residual."""
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        R = Rotation.random(random_state=rng.integers(1 << 30)).as_matrix()
+        tz, A, B, C = rng.normal(size=4) * [0.01, 5, 5, 5]
+        p = rng.normal(size=3) * 0.02
+        e0, J = oracle.residual_jacobian(R, tz, A, B, C, p)
+        h = 1e-6
+        num = np.zeros(6)
+        for j in range(6):
+            def eps_at(delta):
+                d = np.zeros(6)
+                d[j] = delta
+                Rd = Rotation.from_rotvec([d[0], d[1], 0.0]).as_matrix() @ R
+                return oracle.residual_jacobian(Rd, tz + d[2], A + d[3], B + d[4], C + d[5], p)[0]
+            num[j] = (eps_at(h) - eps_at(-h)) / (2 * h)
+        np.testing.assert_allclose(J, num, rtol=1e-6, atol=1e-10)
+        # the residual itself: the parabola of Eq. (2) evaluated in the local frame
+        q = R @ p + np.array([0, 0, tz])
+        assert abs(e0 - (A / 2 * q[0] ** 2 + B * q[0] * q[1] + C / 2 * q[1] ** 2 - q[2])) < 1e-15
+
+
+def test_principal_curvatures_match_eigvalsh():
+    """k1, k2 are the eigenvalues of [[A, B], [B, C]] (Section 3.1.1), k1 >= k2, including
+    near-umbilic cases where the printed T1^2 - AC + B^2 form would cancel."""
+    rng = np.random.default_rng(3)
+    cases = [(10.0003, 1e-4, 10.0), (1.0, 0.0, 1.0), (0.0, 0.0, 0.0), (-3.0, 2.0, 5.0)]
+    cases += [tuple(rng.normal(size=3) * 20) for _ in range(50)]
+    for A, B, C in cases:
+        k1, k2 = oracle.principal_curvatures(A, B, C)
+        ev = np.linalg.eigvalsh(np.array([[A, B], [B, C]]))
+        scale = max(1.0, abs(A) + abs(B) + abs(C))
+        assert k1 >= k2
+        assert abs(k1 - ev[1]) <= 1e-14 * scale
+        assert abs(k2 - ev[0]) <= 1e-14 * scale
+
+
+# --------------------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("radius", [3, 7])
+def test_plane_has_zero_curvature(radius):
+    """A plane is fitted exactly: k1 = k2 = 0, the normal is the plane's, residual 0."""
+    cam = scenes.Camera(48, 40, 100.0, 100.0, 23.5, 19.5)
+    for nrm in ([0.0, 0.0, 1.0], [0.3, -0.2, 1.0], [-0.6, 0.5, 0.7]):
+        sc = scenes.plane_scene(nrm, 1.2, cam)
+        o = oracle.fit_image(sc.depth_m, *_cam(sc), radius=radius, iterations=3, k=1e-5)
+        v = o["flags"] == 1
+        assert v[radius:-radius, radius:-radius].all()
+        assert np.nanmax(np.abs(o["k1"][v])) < 1e-8
+        assert np.nanmax(np.abs(o["k2"][v])) < 1e-8
+        want = np.asarray(nrm) / np.linalg.norm(nrm)
+        assert np.abs(o["normal"][v] - want).max() < 1e-9
+        assert np.nanmax(o["residual"][v]) < 1e-12
+
+
+@pytest.mark.parametrize("radius,distance,f", [(3, 0.7, 131.25), (7, 1.0, 525.0), (11, 0.6, 1050.0)])
+def test_exact_quadric_recovered_at_vertex(radius, distance, f):
+    """A noiseless patch z = A/2 x^2 + B xy + C/2 y^2 whose vertex lies on a pixel ray is
+    fitted exactly there: k1, k2 = eig([[A, B], [B, C]]) and n = the patch axis."""
+    rng = np.random.default_rng(100 + radius)
+    for trial in range(6):
+        A, B, C = rng.uniform(-20, 20, 3)
+        z = np.array([rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5), 1.0])
+        rot = _frame_with_z(z, rng.uniform(0, 2 * np.pi))
+        sc, (u, v) = scenes.quadric_vertex_scene(A, B, C, rot, distance=distance,
+                                                 size=2 * radius + 9, f=f)
+        W = sc.camera.width
+        o = oracle.fit_pixels(sc.depth_m, np.array([v * W + u]), *_cam(sc), radius=radius,
+                              iterations=10, k=1e-5)
+        assert o["flags"][0] == 1
+        ev = np.linalg.eigvalsh([[A, B], [B, C]])
+        assert abs(o["k1"][0] - ev[1]) < 1e-8 * max(1, abs(ev[1]))
+        assert abs(o["k2"][0] - ev[0]) < 1e-8 * max(1, abs(ev[0]))
+        np.testing.assert_allclose(o["normal"][0], rot[:, 2], atol=1e-10)
+        assert o["residual"][0] < 1e-12
+
+
+def _vertex_fit(sc, radius, iterations=10, k=1e-5):
+    c = sc.camera
+    u, v = int(round(c.cx)), int(round(c.cy))
+    o = oracle.fit_pixels(sc.depth_m, np.array([v * c.width + u]), *_cam(sc), radius=radius,
+                          iterations=iterations, k=k)
+    h = radius * sc.depth_m[v, u] / c.fx     # half-extent of the window on the surface
+    return o, h
+
+
+@pytest.mark.parametrize("rho", [0.05, 0.1, 0.2])
+def test_sphere_and_cylinder_at_vertex(rho):
+    """Sphere: k1 = k2 = 1/rho; cylinder: 1/rho and 0, up to the O((h/rho)^2) bias of
+    fitting a parabola to a circle over a window of half-extent h."""
+    cam = scenes.Camera(41, 41, 525.0, 525.0, 20.0, 20.0)
+    sph = scenes.single_shape_scene("sphere", cam, 0.8 + rho, rho)
+    o, h = _vertex_fit(sph, 7)
+    tol = (h / rho) ** 2 / rho
+    assert abs(o["k1"][0] - 1 / rho) < tol and abs(o["k2"][0] - 1 / rho) < tol
+    assert o["k1"][0] - 1 / rho > 0     # the circle bends away faster than its parabola
+    cyl = scenes.single_shape_scene("cylinder", cam, 0.8 + rho, rho, axis=(0.0, 1.0, 0.0))
+    o, h = _vertex_fit(cyl, 7)
+    assert abs(o["k1"][0] - 1 / rho) < tol
+    assert abs(o["k2"][0]) < tol
+
+
+@pytest.mark.parametrize("R", [0.1, 0.4, 1.0])
+def test_saddle_at_vertex(R):
+    """Hyperbolic paraboloid z = (x^2 - y^2)/(2R): k = +-1/R at the vertex, exactly
+    (the surface is itself a parabolic patch)."""
+    cam = scenes.Camera(41, 41, 525.0, 525.0, 20.0, 20.0)
+    rot = _frame_with_z([0.2, -0.1, 1.0], 0.7)
+    sc = scenes.saddle_scene(cam, 0.9, R, rot)
+    o, _ = _vertex_fit(sc, 7)
+    assert abs(o["k1"][0] - 1 / R) < 1e-8 / R
+    assert abs(o["k2"][0] + 1 / R) < 1e-8 / R
+
+
+def test_saddle_off_vertex_tracks_monge_formula():
+    """Away from the vertex the truth is the Monge-patch curvature; the fit's error is
+    bounded by the O(h) bias of a parabola to a non-parabolic local shape."""
+    cam = scenes.Camera(61, 61, 525.0, 525.0, 30.0, 30.0)
+    rot = _frame_with_z([0.0, 0.0, 1.0], 0.3)
+    sc = scenes.saddle_scene(cam, 0.9, 0.3, rot)
+    px = np.array([30 * 61 + 40, 22 * 61 + 30, 38 * 61 + 36])
+    o = oracle.fit_pixels(sc.depth_m, px, *_cam(sc), radius=5, iterations=10, k=1e-5)
+    k1t = sc.k1_true.ravel()[px]
+    k2t = sc.k2_true.ravel()[px]
+    h = 5 * 0.9 / 525.0
+    assert np.all(np.abs(o["k1"] - k1t) < 0.2 * h / 0.3 ** 2)
+    assert np.all(np.abs(o["k2"] - k2t) < 0.2 * h / 0.3 ** 2)
+
+
+def test_table1_synthetic_rows():
+    """Table 1 (synthetic objects, 37x37 patch): a 10 cm sphere has expected and computed
+    curvature 0.010 / 0.010 mm^-1 and a 9 cm cylinder 0.0111 / ~0 mm^-1, printed to those
+    digits.  The paper does not give the camera or distance, so the oracle is run
+    noiselessly with the 37x37 window spanning one twentieth of the radius (where the
+    O((h/r)^2) truncation bias is below the printed precision); its values must round to
+    the printed ones, which fixes the units (mm^-1 = 1e-3 m^-1) and the sign convention
+    (positive for a surface bulging toward the camera)."""
+    with open(os.path.join(GOLDEN, "table1_synthetic.json")) as f:
+        rows = json.load(f)["rows"]
+    for row in rows:
+        rho = row["radius_mm"] / 1000.0
+        dist = 0.6
+        f = 18 * dist / (0.05 * rho)
+        cam = scenes.Camera(45, 45, f, f, 22.0, 22.0)
+        sc = scenes.single_shape_scene(row["shape"], cam, dist + rho, rho, axis=(1.0, 0.0, 0.0))
+        o, _ = _vertex_fit(sc, 18, iterations=8)
+        k1_mm, k2_mm = o["k1"][0] / 1000.0, o["k2"][0] / 1000.0
+        digits = row["printed_digits"]
+        assert round(k1_mm, digits) == pytest.approx(row["computed_k_max_mm"], abs=1e-12)
+        assert round(k2_mm, digits) == pytest.approx(round(row["computed_k_min_mm"], digits),
+                                                     abs=1e-12)
+
+
+# --------------------------------------------------------------------------- the solver
+
+def _patch_points(sc, u, v, r):
+    c = sc.camera
+    pts = []
+    centre = None
+    for dv in range(-r, r + 1):
+        for du in range(-r, r + 1):
+            Z = sc.depth_m[v + dv, u + du]
+            if Z <= 0:
+                continue
+            if du == 0 and dv == 0:
+                centre = len(pts)
+            pts.append([Z * (u + du - c.cx) / c.fx, Z * (v + dv - c.cy) / c.fy, Z])
+    return np.array(pts), centre
+
+
+def _lstsq_normal(pts):
+    """Unit normal of the least-squares plane z = a x + b y + c, facing away from the
+    camera (brute force with numpy.linalg.lstsq)."""
+    M = np.c_[pts[:, 0], pts[:, 1], np.ones(len(pts))]
+    (a, b, _), *_ = np.linalg.lstsq(M, pts[:, 2], rcond=None)
+    n = np.array([-a, -b, 1.0])
+    return n / np.linalg.norm(n)
+
+
+def test_initial_normal_is_least_squares_plane():
+    """With zero iterations the refined normal is the initial normal of Eq. (7), i.e.
+    the normal of the least-squares plane through the 7x7 window."""
+    sc = scenes.sphere_on_plane(noise=True)
+    o = oracle.fit_image(sc.depth_m, *_cam(sc), radius=3, iterations=0, k=1e-5)
+    for (u, v) in [(80, 60), (70, 52), (95, 66), (10, 10), (150, 110)]:
+        pts, _ = _patch_points(sc, u, v, 3)
+        np.testing.assert_allclose(o["normal"][v, u], _lstsq_normal(pts), atol=1e-10)
+        assert o["k1"][v, u] == 0.0 and o["k2"][v, u] == 0.0
+
+
+def _model_residuals(x, pts_c, R0):
+    """The parabolic patch of Eq. (2) in the frame Exp([ax, ay, 0]x) R0 shifted by t_z."""
+    ax, ay, tz, A, B, C = x
+    R = Rotation.from_rotvec([ax, ay, 0.0]).as_matrix() @ R0
+    q = pts_c @ R.T
+    q[:, 2] += tz
+    return A / 2 * q[:, 0] ** 2 + B * q[:, 0] * q[:, 1] + C / 2 * q[:, 1] ** 2 - q[:, 2]
+
+
+def _min_rotation_to_z(n):
+    v = np.cross(n, [0, 0, 1.0])
+    s = np.linalg.norm(v)
+    if s < 1e-300:
+        return np.eye(3)
+    return Rotation.from_rotvec(v / s * math.atan2(s, n[2])).as_matrix()
+
+
+def test_one_step_is_weighted_gauss_newton():
+    """T = 1: the parameters after one step are x0 - (J^T W J)^{-1} J^T W e (Eq. (10))
+    with W = k/(k + e^2) (Eq. (11)), J taken by finite differences of the model."""
+    sc = scenes.sphere_on_plane(noise=True)
+    k = 4e-6
+    for (u, v) in [(80, 60), (74, 57), (88, 64)]:
+        pts, ci = _patch_points(sc, u, v, 3)
+        n0 = _lstsq_normal(pts)
+        pc = pts - pts[ci]
+        R0 = _min_rotation_to_z(n0)
+        x0 = np.zeros(6)
+        e = _model_residuals(x0, pc, R0)
+        J = np.zeros((len(pc), 6))
+        for j in range(6):
+            d = np.zeros(6)
+            d[j] = 1e-7
+            J[:, j] = (_model_residuals(x0 + d, pc, R0) - _model_residuals(x0 - d, pc, R0)) / 2e-7
+        w = k / (k + e ** 2)
+        b = np.linalg.solve(J.T @ (w[:, None] * J), J.T @ (w * e))
+        x1 = x0 - b
+        ev = np.linalg.eigvalsh([[x1[3], x1[4]], [x1[4], x1[5]]])
+        n1 = (Rotation.from_rotvec([x1[0], x1[1], 0]).as_matrix() @ R0)[2]
+        o = oracle.fit_patch(pts, ci, n0, iterations=1, k=k)
+        assert abs(o["k1"] - ev[1]) < 1e-5 * max(1, abs(ev[1]))
+        assert abs(o["k2"] - ev[0]) < 1e-5 * max(1, abs(ev[0]))
+        np.testing.assert_allclose(o["normal"], n1, atol=1e-8)
+
+
+def _scipy_fit(pts, ci, n0, loss, k):
+    pc = pts - pts[ci]
+    R0 = _min_rotation_to_z(n0)
+    sol = least_squares(_model_residuals, np.zeros(6), args=(pc, R0), loss=loss,
+                        f_scale=math.sqrt(k), xtol=1e-15, ftol=1e-15, gtol=1e-15,
+                        max_nfev=20000, method="trf")
+    x = sol.x
+    ev = np.linalg.eigvalsh([[x[3], x[4]], [x[4], x[5]]])
+    n = (Rotation.from_rotvec([x[0], x[1], 0]).as_matrix() @ R0)[2]
+    return ev[1], ev[0], n
+
+
+@pytest.mark.parametrize("loss,k", [("cauchy", 4e-6), ("cauchy", 1e-5), ("linear", 1e12)])
+def test_converged_irls_is_the_cauchy_m_estimator(loss, k):
+    """Iterating the re-weighting of Eq. (11) to convergence minimises the Cauchy loss
+    sum log(1 + e^2/k); SciPy's trust-region solver (a different algorithm and
+    parameterisation) must land on the same k1, k2 and normal.  k -> infinity gives
+    plain nonlinear least squares."""
+    sc = scenes.sphere_on_plane(noise=True)
+    for (u, v) in [(80, 60), (76, 55), (86, 63)]:
+        pts, ci = _patch_points(sc, u, v, 5)
+        pts7, _ = _patch_points(sc, u, v, 3)
+        n0 = _lstsq_normal(pts7)
+        k1s, k2s, ns = _scipy_fit(pts, ci, n0, loss, k)
+        o = oracle.fit_patch(pts, ci, n0, iterations=300, k=k)
+        assert abs(o["k1"] - k1s) < 1e-6 * max(1, abs(k1s))
+        assert abs(o["k2"] - k2s) < 1e-6 * max(1, abs(k2s))
+        np.testing.assert_allclose(o["normal"], ns, atol=1e-9)
+
+
+# --------------------------------------------------------------------------- invariances
+
+def test_rigid_motion_invariance():
+    """Moving the points rigidly (and the initial normal with them) leaves k1, k2 and the
+    residual unchanged and rotates the refined normal."""
+    sc = scenes.sphere_on_plane(noise=True)
+    rng = np.random.default_rng(8)
+    for (u, v) in [(80, 60), (72, 58), (40, 30)]:
+        pts, ci = _patch_points(sc, u, v, 5)
+        n0 = _lstsq_normal(_patch_points(sc, u, v, 3)[0])
+        base = oracle.fit_patch(pts, ci, n0, iterations=5, k=1e-5)
+        for _ in range(3):
+            Q = Rotation.from_rotvec(rng.normal(size=3) * 0.4).as_matrix()
+            t = rng.normal(size=3)
+            o = oracle.fit_patch(pts @ Q.T + t, ci, Q @ n0, iterations=5, k=1e-5)
+            assert abs(o["k1"] - base["k1"]) < 1e-9 * max(1, abs(base["k1"]))
+            assert abs(o["k2"] - base["k2"]) < 1e-9 * max(1, abs(base["k2"]))
+            assert abs(o["residual"] - base["residual"]) < 1e-9 * base["residual"] + 1e-15
+            np.testing.assert_allclose(o["normal"], Q @ base["normal"], atol=1e-9)
+
+
+def _sym_scene():
+    cam = scenes.Camera(64, 64, 60.0, 60.0, 31.5, 31.5)
+    return scenes.cluttered_scene(cam, seed_frame=2, config_index=9, noise=True, dropout=0.02)
+
+
+def test_image_mirror_and_transpose_symmetry():
+    """With cx = (W-1)/2, cy = (H-1)/2, fx = fy, W = H: mirroring u or v, or transposing
+    the image, mirrors k1, k2 and the residual (up to summation order)."""
+    sc = _sym_scene()
+    d = sc.depth_m
+    kw = dict(radius=4, iterations=4, k=1e-5)
+    base = oracle.fit_image(d, *_cam(sc), **kw)
+    v = base["flags"] == 1
+    assert v.mean() > 0.8
+    for tf in (lambda a: a[:, ::-1], lambda a: a[::-1, :], lambda a: a.T):
+        o = oracle.fit_image(np.ascontiguousarray(tf(d)), *_cam(sc), **kw)
+        assert np.array_equal(tf(v), o["flags"] == 1)
+        for key in ("k1", "k2", "residual"):
+            a, b = tf(base[key])[tf(v)], o[key][tf(v)]
+            assert np.abs(a - b).max() <= 1e-7 * np.maximum(1, np.abs(a)).max()
+
+
+def test_scale_covariance_exact_for_power_of_two():
+    """Depth x s with k x s^2 gives k1, k2 x 1/s and residual x s; for s = 2 every
+    operation scales exactly, so the results must be bit-identical after rescaling."""
+    sc = _sym_scene()
+    base = oracle.fit_image(sc.depth_m, *_cam(sc), radius=4, iterations=3, k=1e-5)
+    o2 = oracle.fit_image(sc.depth_m * 2, *_cam(sc), radius=4, iterations=3, k=4e-5)
+    v = base["flags"] == 1
+    assert np.array_equal(v, o2["flags"] == 1)
+    assert np.array_equal(base["k1"][v], o2["k1"][v] * 2)
+    assert np.array_equal(base["k2"][v], o2["k2"][v] * 2)
+    assert np.array_equal(base["residual"][v] * 2, o2["residual"][v])
+    o3 = oracle.fit_image(sc.depth_m * 3, *_cam(sc), radius=4, iterations=3, k=9e-5)
+    a, b = base["k1"][v], o3["k1"][v] * 3
+    assert np.abs(a - b).max() <= 1e-6 * np.maximum(1, np.abs(a)).max()
+
+
+# --------------------------------------------------------------------------- degenerate inputs
+
+def test_invalid_and_degenerate_pixels():
+    """No depth at the centre, too few neighbours, or a collinear neighbourhood give an
+    invalid pixel (NaN, flag 0); image borders clip the window."""
+    cam = scenes.Camera(20, 16, 30.0, 30.0, 9.5, 7.5)
+    sc = scenes.plane_scene([0.1, 0.2, 1.0], 1.0, cam)
+    d = sc.depth_m.copy()
+    d[5, 5] = 0.0                      # hole at a centre
+    d[10:, :] = 0.0                    # bottom block empty
+    d[12, :] = sc.depth_m[12, :]       # a single row surrounded by holes
+    o = oracle.fit_image(d, *_cam(sc), radius=2, iterations=3, k=1e-5)
+    assert o["flags"][5, 5] == 0 and np.isnan(o["k1"][5, 5])
+    assert (o["flags"][12, :] == 0).all()   # collinear: normal regression singular
+    assert o["flags"][0, 0] == 1             # corner: clipped window still has 9 points
+    assert abs(o["k1"][0, 0]) < 1e-8
+    # an isolated valid pixel
+    d2 = np.zeros_like(d)
+    d2[8, 8] = 1.0
+    o2 = oracle.fit_image(d2, *_cam(sc), radius=2, iterations=3, k=1e-5)
+    assert o2["flags"].sum() == 0
+
+
+def test_rejection_filter_removes_gross_outlier():
+    """Eq. (11) with R = 2 MSE: a gross outlier in an exact quadric patch is rejected,
+    so the fit recovers the quadric exactly; without rejection it only down-weights it.
+    On an exact patch (MSE = 0) nothing is rejected."""
+    rng = np.random.default_rng(4)
+    A, B, C = 8.0, -2.0, 3.0
+    rot = _frame_with_z([0.1, 0.2, 1.0], 0.5)
+    sc, (u, v) = scenes.quadric_vertex_scene(A, B, C, rot, distance=0.9, size=23, f=525.0)
+    pts, ci = _patch_points(sc, u, v, 7)
+    n0 = _lstsq_normal(_patch_points(sc, u, v, 3)[0])
+    ev = np.linalg.eigvalsh([[A, B], [B, C]])
+    exact = oracle.fit_patch(pts, ci, n0, iterations=8, k=1e-6, reject=True)
+    assert abs(exact["k1"] - ev[1]) < 1e-8 and exact["valid"]
+    bad = pts.copy()
+    j = (ci + 17) % len(pts)
+    bad[j] *= 1.03                     # push one point 3% further along its ray
+    rej = oracle.fit_patch(bad, ci, n0, iterations=8, k=1e-6, reject=True)
+    keep = oracle.fit_patch(bad, ci, n0, iterations=8, k=1e-6, reject=False)
+    assert abs(rej["k1"] - ev[1]) < 1e-8 and abs(rej["k2"] - ev[0]) < 1e-8
+    assert abs(keep["k1"] - ev[1]) + abs(keep["k2"] - ev[0]) > 1e-6
