@@ -1,0 +1,153 @@
+"""Shared test helpers: run the GPU library and the oracle on the same seeded input and
+compare them element by element."""
+from __future__ import annotations
+
+import sys
+from typing import Dict, Optional
+
+import numpy as np
+
+KAPPA_FLOOR = 1.0   # m^-1: relative errors are taken against max(|k|, 1 m^-1)
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def as_oracle_depth(depth: np.ndarray, fmt: str, scale: float = 1e-3) -> np.ndarray:
+    """The exact metres the GPU library reads from `depth` (f64, 0 = no depth)."""
+    if fmt == "u16":
+        d = depth.astype(np.float64) * np.float64(np.float32(scale))
+    elif fmt == "f16":
+        d = depth.astype(np.float16).astype(np.float64)
+    else:
+        d = depth.astype(np.float32).astype(np.float64)
+    d[~np.isfinite(d) | (d <= 0)] = 0.0
+    return d
+
+
+# Relative size of the input perturbation used to probe whether a pixel's result is
+# determined by its input: about the accumulated relative rounding error of an FP64
+# evaluation of the fit (sqrt(1e5 operations) * 2^-53 ~ 3e-14), rounded up to 2^-44.
+PERTURBATION = 2.0 ** -44
+
+
+def oracle_fit(depth, fmt, cam, radius, iterations, k, normal_radius=3, scale=1e-3, pixels=None,
+               perturb=0):
+    """The oracle on the GPU's exact input.  perturb=s (s > 0) multiplies every depth by
+    1 +- PERTURBATION with signs drawn from seed s: a rounding-level change of the input
+    that shows which pixels' results are not determined by the input at the tolerance."""
+    import oracle
+    d = as_oracle_depth(depth, fmt, scale)
+    if perturb:
+        sign = np.random.default_rng([20170703, perturb]).choice([-1.0, 1.0], size=d.shape)
+        d = np.where(d > 0, d * (1.0 + sign * PERTURBATION), 0.0)
+    K = [float(np.float32(x)) for x in (cam.fx, cam.fy, cam.cx, cam.cy)]
+    kk = float(np.float32(k))
+    if pixels is None:
+        return oracle.fit_image(d, *K, radius=radius, iterations=iterations, k=kk,
+                                normal_radius=normal_radius)
+    return oracle.fit_pixels(d, pixels, *K, radius=radius, iterations=iterations, k=kk,
+                             normal_radius=normal_radius)
+
+
+def oracle_pair(depth, fmt, cam, radius, iterations, k, normal_radius=3, scale=1e-3, pixels=None):
+    """The oracle and its sensitivity probe: the probe result holds, per pixel, the
+    perturbed run (of two, differently seeded) that is farthest from the oracle."""
+    kw = dict(normal_radius=normal_radius, scale=scale, pixels=pixels)
+    o = oracle_fit(depth, fmt, cam, radius, iterations, k, **kw)
+    a = oracle_fit(depth, fmt, cam, radius, iterations, k, perturb=1, **kw)
+    b = oracle_fit(depth, fmt, cam, radius, iterations, k, perturb=2, **kw)
+    ea = np.maximum(rel_err(a["k1"], o["k1"]), rel_err(a["k2"], o["k2"]))
+    eb = np.maximum(rel_err(b["k1"], o["k1"]), rel_err(b["k2"], o["k2"]))
+    take_b = (eb > ea) | np.isnan(eb) | (b["flags"] != o["flags"])
+    alt = {}
+    for key in a:
+        tb = take_b if a[key].ndim == take_b.ndim else take_b[..., None]
+        alt[key] = np.where(tb, b[key], a[key])
+    return o, alt
+
+
+def to_device_depth(depth: np.ndarray, fmt: str, device="cuda:0"):
+    import torch
+    if fmt == "u16":
+        t = torch.from_numpy(np.ascontiguousarray(depth.astype(np.uint16)).view(np.int16))
+    elif fmt == "f16":
+        t = torch.from_numpy(np.ascontiguousarray(depth.astype(np.float16)))
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(depth.astype(np.float32)))
+    return t.to(device)
+
+
+def gpu_fit(ctx, depth, fmt, cam, normal=True, residual=True, **kw) -> Dict[str, np.ndarray]:
+    import torch
+    t = to_device_depth(depth, fmt)
+    out = ctx.fit(t, (cam.fx, cam.fy, cam.cx, cam.cy), normal=normal, residual=residual, **kw)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    res["refits"] = ctx.last_refit_count()
+    return res
+
+
+def rel_err(a, b):
+    return np.abs(a.astype(np.float64) - b) / np.maximum(np.abs(b), KAPPA_FLOOR)
+
+
+def compare(g: Dict[str, np.ndarray], o: Dict[str, np.ndarray], tol: float, name: str,
+            o_alt: Optional[Dict[str, np.ndarray]] = None, max_nonunique: float = 0.01,
+            normal_tol: Optional[float] = None, residual_tol: Optional[float] = None) -> dict:
+    """Element-by-element parity of the GPU result `g` with the oracle `o`.
+
+    A pixel's curvature is *unique* at the tolerance when the oracle gives it, to within
+    tol/10, also for rounding-level perturbed input (`o_alt`, see oracle_pair).  Every unique
+    pixel must be valid on the GPU and agree within `tol` (relative, floor 1 m^-1) in k1
+    and k2 (and normal / residual when asked).  Validity must agree wherever both oracle
+    runs agree on it.  Non-unique pixels (chaotic iterations, e.g. at depth edges) are
+    counted and reported; they may not exceed `max_nonunique` of the image."""
+    gv = (g["flags"] & 1) == 1
+    ov = o["flags"] == 1
+    if o_alt is not None:
+        av = o_alt["flags"] == 1
+        sens = np.maximum(rel_err(o_alt["k1"], o["k1"]), rel_err(o_alt["k2"], o["k2"]))
+        unique = ov & av & (sens <= tol / 10)
+        valid_known = ov == av
+    else:
+        unique = ov.copy()
+        valid_known = np.ones_like(ov)
+    nonunique = int(np.sum(ov & ~unique)) + int(np.sum(~valid_known))
+    e = np.maximum(rel_err(g["k1"], o["k1"]), rel_err(g["k2"], o["k2"]))
+    eu = e[unique & gv]
+    mism = int(np.sum((gv != ov) & valid_known))
+    stats = dict(name=name, pixels=int(gv.size), valid=int(ov.sum()), unique=int(unique.sum()),
+                 nonunique=nonunique, flag_mismatch=mism, refits=int(g.get("refits", 0)),
+                 max_err=float(eu.max()) if eu.size else 0.0,
+                 rms_err=float(np.sqrt(np.mean(eu ** 2))) if eu.size else 0.0,
+                 n_over=int(np.sum(e[unique] > tol) + np.sum(unique & ~gv)))
+    if (ov & ~unique).any():
+        stats["max_err_nonunique"] = float(np.nanmax(e[ov & ~unique & gv])) if (ov & ~unique & gv).any() else 0.0
+    fp32 = unique & gv & ((g["flags"] & 2) == 0)
+    if fp32.any():
+        stats["max_err_fp32_pixels"] = float(e[fp32].max())
+    log("  parity", stats)
+    if stats["n_over"]:
+        idx = np.argwhere(unique & ((e > tol) | ~gv))[:8]
+        for ij in idx:
+            ij = tuple(ij)
+            log("   over:", ij, "gpu", g["k1"][ij], g["k2"][ij], "oracle", o["k1"][ij], o["k2"][ij],
+                "flags", int(g["flags"][ij]), "err", float(e[ij]))
+    assert mism == 0, f"{name}: validity differs at {mism} pixels"
+    assert stats["n_over"] == 0, f"{name}: {stats['n_over']} pixels beyond {tol}"
+    assert nonunique <= max_nonunique * gv.size, f"{name}: {nonunique} non-unique pixels"
+    # invalid pixels carry NaN; k1 >= k2
+    assert np.all(np.isnan(g["k1"][~gv])) and np.all(np.isnan(g["k2"][~gv]))
+    assert np.all(g["k1"][gv] >= g["k2"][gv])
+    if normal_tol is not None and "normal" in g:
+        dn = np.abs(g["normal"][unique] - o["normal"][unique]).max() if unique.any() else 0.0
+        log("  normal max abs diff", float(dn))
+        assert dn <= normal_tol
+    if residual_tol is not None and "residual" in g:
+        rr = np.abs(g["residual"][unique] - o["residual"][unique]) / np.maximum(o["residual"][unique], 1e-6)
+        log("  residual max rel diff (floor 1 um)", float(rr.max()) if rr.size else 0.0)
+        assert rr.size == 0 or rr.max() <= residual_tol
+    return stats

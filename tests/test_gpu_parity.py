@@ -1,0 +1,97 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on the same
+seeded inputs, element by element.
+
+Tolerance (relative, against max(|k|, 1 m^-1)): 1e-4 on noiseless input, 1e-3 on noisy
+input, in k1 and k2 of every pixel whose oracle result is unique at that tolerance (see
+tests/helpers.compare).  FP64 mode must agree to 2e-7: its outputs are stored as FP32,
+whose rounding alone is up to 2^-24 relative.
+"""
+import numpy as np
+import pytest
+
+from paper_1707_00385_amd import scenes
+from tests.helpers import compare, gpu_fit, log, oracle_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1707_00385_amd.api import Context
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _run(ctx, name, depth, fmt, cam, radius, iterations, tol, precision="mixed", k=1e-5,
+         normal_radius=3, **kw):
+    log(f"[case] {name} fmt={fmt} {cam.width}x{cam.height} r={radius} T={iterations} {precision}")
+    g = gpu_fit(ctx, depth, fmt, cam, radius=radius, iterations=iterations, k=k,
+                normal_radius=normal_radius, precision=precision)
+    o, oa = oracle_pair(depth, fmt, cam, radius, iterations, k, normal_radius=normal_radius)
+    return compare(g, o, tol, name, o_alt=oa, **kw), g, o
+
+
+def test_sphere_on_plane_160x120(ctx):
+    """The small workload: sphere r = 0.10 m on a plane, r = 3, T = 3, FP32 metres."""
+    for noise, tol in ((False, 1e-4), (True, 1e-3)):
+        sc = scenes.sphere_on_plane(noise=noise)
+        _run(ctx, f"sphere_on_plane noise={noise}", sc.depth_m, "f32", sc.camera, 3, 3, tol,
+             normal_tol=1e-3, residual_tol=1e-2)
+
+
+def test_fp64_mode_matches_oracle_tightly(ctx):
+    """FP64 mode runs the oracle's steps in double precision on the GPU."""
+    sc = scenes.cluttered_scene(scenes.Camera(96, 72, 80.0, 80.0, 47.5, 35.5), seed_frame=5,
+                                config_index=7)
+    _run(ctx, "fp64 clutter", sc.depth_u16(), "u16", sc.camera, 5, 5, 2e-7, precision="fp64",
+         normal_tol=2e-7, residual_tol=2e-7)
+
+
+@pytest.mark.parametrize("fmt", ["u16", "f16", "f32"])
+def test_clutter_small_formats(ctx, fmt):
+    """Spans several 16x16 tiles and a ragged tail (100x75); noisy input, r = 5, T = 5."""
+    cam = scenes.Camera(100, 75, 90.0, 90.0, 49.5, 37.0)
+    sc = scenes.cluttered_scene(cam, seed_frame=3, config_index=8)
+    depth = sc.depth_u16() if fmt == "u16" else sc.depth_m
+    _run(ctx, f"clutter100x75 {fmt}", depth, fmt, cam, 5, 5, 1e-3)
+
+
+def test_vga_headline_full_frame(ctx):
+    """The headline frame: 640x480 Kinect-like u16, r = 7, T = 5, every pixel."""
+    sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=0, config_index=1)
+    st, g, o = _run(ctx, "vga u16 noisy", sc.depth_u16(), "u16", sc.camera, 7, 5, 1e-3)
+    log("  refit fraction", st["refits"] / st["pixels"])
+
+
+def test_vga_noiseless_full_frame(ctx):
+    sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=1, config_index=1, noise=False,
+                                dropout=0.0)
+    _run(ctx, "vga f32 noiseless", sc.depth_m, "f32", sc.camera, 7, 5, 1e-4)
+
+
+@pytest.mark.parametrize("w,h,r", [(1, 1, 1), (5, 3, 2), (17, 16, 3), (33, 31, 18)])
+def test_tiny_and_ragged_images(ctx, w, h, r):
+    cam = scenes.Camera(w, h, 40.0, 40.0, (w - 1) / 2, (h - 1) / 2)
+    sc = scenes.cluttered_scene(cam, seed_frame=w * 100 + h, config_index=9, n_objects=3)
+    _run(ctx, f"tiny {w}x{h}", sc.depth_m, "f32", cam, r, 4, 1e-3)
+
+
+def test_all_invalid_and_zero_iterations(ctx):
+    cam = scenes.Camera(40, 30, 40.0, 40.0, 19.5, 14.5)
+    z = np.zeros((30, 40), np.float32)
+    g = gpu_fit(ctx, z, "f32", cam, radius=3, iterations=5)
+    assert (g["flags"] == 0).all() and np.isnan(g["k1"]).all()
+    sc = scenes.cluttered_scene(cam, seed_frame=4, config_index=9)
+    _run(ctx, "T=0", sc.depth_m, "f32", cam, 3, 0, 1e-4, normal_tol=1e-4)
+
+
+def test_deterministic_repeat(ctx):
+    sc = scenes.cluttered_scene(scenes.Camera(64, 48, 60.0, 60.0, 31.5, 23.5), seed_frame=6,
+                                config_index=9)
+    a = gpu_fit(ctx, sc.depth_u16(), "u16", sc.camera, radius=4, iterations=5)
+    b = gpu_fit(ctx, sc.depth_u16(), "u16", sc.camera, radius=4, iterations=5)
+    for key in ("k1", "k2", "normal", "residual", "flags"):
+        assert np.array_equal(a[key], b[key], equal_nan=True), key
