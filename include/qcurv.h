@@ -101,7 +101,7 @@ typedef struct {
 typedef struct qc_context qc_context;
 
 /* Defaults: r = 7, r_n = 3, T = 5, k = 1e-5 m^2, depth_scale = 1e-3, MIXED,
- * cond_max = 30, step_max = 1e-2. */
+ * cond_max = 30, step_max = 0.1. */
 void qc_params_default(qc_params* params);
 
 /* Creates a context bound to HIP device `device`.  *ctx receives the handle. */
@@ -119,6 +119,20 @@ qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params
 /* Number of pixels recomputed in FP64 by the most recent qc_fit on this context
  * (MIXED), or flagged (FP32).  Synchronises with that call's stream. */
 qc_status qc_last_refit_count(qc_context* ctx, uint32_t* count);
+
+/* Kernel timing.  With timing enabled, every qc_fit on the context records HIP events
+ * around its kernels on the call's stream: the FP32 (or FP64-only) fitting pass and the
+ * FP64 recomputation pass.  qc_get_timing waits for the recorded events, returns the
+ * sums since the last reset (milliseconds) and, if `reset` is non-zero, clears them.
+ * Timing adds two or three event records per call and is off by default. */
+typedef struct {
+    uint64_t calls;       /* qc_fit calls timed */
+    double fit_ms;        /* summed duration of the tiled fitting pass */
+    double refit_ms;      /* summed duration of the FP64 recomputation pass (MIXED) */
+} qc_timing;
+
+qc_status qc_set_timing(qc_context* ctx, int enable);
+qc_status qc_get_timing(qc_context* ctx, qc_timing* out, int reset);
 
 /* The HIP error code behind the last QC_ERR_HIP on this context (0 if none). */
 int qc_last_hip_error(qc_context* ctx);

@@ -19,7 +19,7 @@ QC_MAX_RADIUS = 18
 
 # Every exported symbol declared in include/qcurv.h.
 EXPORTS = ["qc_params_default", "qc_create", "qc_destroy", "qc_fit", "qc_last_refit_count",
-           "qc_last_hip_error", "qc_status_string"]
+           "qc_set_timing", "qc_get_timing", "qc_last_hip_error", "qc_status_string"]
 
 
 class Intrinsics(ctypes.Structure):
@@ -44,6 +44,11 @@ class Frame(ctypes.Structure):
 class Output(ctypes.Structure):
     _fields_ = [("k1", ctypes.c_void_p), ("k2", ctypes.c_void_p), ("normal", ctypes.c_void_p),
                 ("residual", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_uint64), ("fit_ms", ctypes.c_double),
+                ("refit_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -78,6 +83,10 @@ def load() -> ctypes.CDLL:
     lib.qc_fit.restype = ctypes.c_int
     lib.qc_last_refit_count.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
     lib.qc_last_refit_count.restype = ctypes.c_int
+    lib.qc_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.qc_set_timing.restype = ctypes.c_int
+    lib.qc_get_timing.argtypes = [vp, ctypes.POINTER(Timing), ctypes.c_int]
+    lib.qc_get_timing.restype = ctypes.c_int
     lib.qc_last_hip_error.argtypes = [vp]
     lib.qc_last_hip_error.restype = ctypes.c_int
     lib.qc_status_string.argtypes = [ctypes.c_int]

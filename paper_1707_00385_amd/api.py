@@ -46,6 +46,21 @@ def depth_format(t: torch.Tensor) -> int:
     raise TypeError(f"unsupported depth dtype {t.dtype}")
 
 
+def upload_depth(depth, fmt: str, device="cuda:0") -> torch.Tensor:
+    """Copies a host depth image (numpy) to the GPU in the given sample format: "u16"
+    (carried as int16 bits), "f16" or "f32"."""
+    import numpy as np
+    if fmt == "u16":
+        t = torch.from_numpy(np.ascontiguousarray(np.asarray(depth).astype(np.uint16)).view(np.int16))
+    elif fmt == "f16":
+        t = torch.from_numpy(np.ascontiguousarray(np.asarray(depth).astype(np.float16)))
+    elif fmt == "f32":
+        t = torch.from_numpy(np.ascontiguousarray(np.asarray(depth).astype(np.float32)))
+    else:
+        raise ValueError(f"unknown depth format {fmt}")
+    return t.to(device)
+
+
 def make_frame(depth: torch.Tensor, K: Sequence[float]) -> _lib.Frame:
     if depth.dim() != 2 or not depth.is_cuda:
         raise ValueError("depth must be a 2-D tensor on a GPU")
@@ -123,6 +138,15 @@ class Context:
                                     ctypes.byref(output_struct(out)),
                                     ctypes.c_void_p(st.cuda_stream)), "qc_fit")
         return out
+
+    def set_timing(self, enable: bool) -> None:
+        _lib.check(self._lib.qc_set_timing(self._h, int(bool(enable))), "qc_set_timing")
+
+    def get_timing(self, reset: bool = False) -> dict:
+        t = _lib.Timing()
+        _lib.check(self._lib.qc_get_timing(self._h, ctypes.byref(t), int(bool(reset))),
+                   "qc_get_timing")
+        return {"calls": int(t.calls), "fit_ms": float(t.fit_ms), "refit_ms": float(t.refit_ms)}
 
     def last_refit_count(self) -> int:
         n = ctypes.c_uint32()

@@ -30,8 +30,10 @@ struct FitDesc {
 // `masks`, both of refit_capacity() entries; counts[0] = entries, counts[1] = pixels,
 // zeroed here), then for MIXED an FP64 pass over those pixels.  FP64: one tiled FP64
 // pass over every pixel.
+// `events` (optional, 3 entries) are recorded before the fitting pass, after it, and
+// after the recomputation pass.
 hipError_t launch_fit(const FitDesc& d, uint32_t* entries, uint64_t* masks, uint32_t* counts,
-                      hipStream_t stream);
+                      hipStream_t stream, hipEvent_t* events = nullptr);
 
 // Entries needed by launch_fit for a width x height frame.
 int64_t refit_capacity(int width, int height);

@@ -130,6 +130,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
     out.k1 = out.k2 = out.residual = nan;
     out.n[0] = out.n[1] = out.n[2] = nan;
     out.flags = 0;
+    using Acc = double;   // normal-equation sums and the 6x6 solve
     const int radius = RC > 0 ? RC : d.radius;
     const bool fp32 = sizeof(Real) == 4;
 
@@ -208,7 +209,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
         R[2][0] = -wy;                    R[2][1] = wx;                     R[2][2] = n0z;
     }
     Real tz = 0, A = 0, B = 0, C = 0;     // patch coefficients in units of h
-    Real kappa_max = 0, last_step = 0;
+    Acc kappa_max = 0, last_step = 0;
 
     for (int it = 0; it < d.iterations; ++it) {
         // R' = R G: maps m straight to the rotated, scaled, centred point s = R p'/h.
@@ -224,10 +225,12 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
         const Real Ah = Real(0.5) * A, Bh = Real(0.5) * B, Ch = Real(0.5) * C;
         // accumulators: Hij = sum ji jj with j = sqrt(w) * (J0, J1, -1, sx^2, sx sy, sy^2);
         // S_i = sum ji sqrt(w) (column 2 up to sign); Gi = sum ji sqrt(w) e.
-        Real H00 = 0, H01 = 0, H03 = 0, H04 = 0, H05 = 0, H11 = 0, H13 = 0, H14 = 0, H15 = 0;
-        Real H33 = 0, H34 = 0, H35 = 0, H45 = 0, H55 = 0;
-        Real S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0;
-        Real G0 = 0, G1 = 0, G2 = 0, G3 = 0, G4 = 0, G5 = 0;
+        // The sums are accumulated in FP64 whatever the per-neighbour precision: FP32
+        // accumulation of 225 terms is the dominant rounding error of the FP32 fit.
+        Acc H00 = 0, H01 = 0, H03 = 0, H04 = 0, H05 = 0, H11 = 0, H13 = 0, H14 = 0, H15 = 0;
+        Acc H33 = 0, H34 = 0, H35 = 0, H45 = 0, H55 = 0;
+        Acc S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0;
+        Acc G0 = 0, G1 = 0, G2 = 0, G3 = 0, G4 = 0, G5 = 0;
         for_window<RC, sizeof(Real) == 8>(src, radius, [&](float2 t, int du, int dv) {
             const Real D = Real(t.x);
             const Real dD = D - g.Dc;
@@ -243,82 +246,84 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             const Real rw = rsqrtT(den);                    // sqrt of the weight, Eq. (11)
             const Real J0 = -fmaT(cp, sz2, sy);             // de/dtheta_x
             const Real J1 = fmaT(ap, sz2, sx);              // de/dtheta_y
-            const Real j0 = rw * J0, j1 = rw * J1;
+            const Real j0r = rw * J0, j1r = rw * J1;
             const Real xr = rw * sx, yr = rw * sy;
-            const Real j3 = xr * sx, j4 = xr * sy, j5 = yr * sy, je = rw * e;
+            const Real j3r = xr * sx, j4r = xr * sy, j5r = yr * sy, jer = rw * e;
+            const Acc j0 = Acc(j0r), j1 = Acc(j1r), wr = Acc(rw);
+            const Acc j3 = Acc(j3r), j4 = Acc(j4r), j5 = Acc(j5r), je = Acc(jer);
             H00 = fmaT(j0, j0, H00); H01 = fmaT(j0, j1, H01); H03 = fmaT(j0, j3, H03);
             H04 = fmaT(j0, j4, H04); H05 = fmaT(j0, j5, H05);
             H11 = fmaT(j1, j1, H11); H13 = fmaT(j1, j3, H13); H14 = fmaT(j1, j4, H14);
             H15 = fmaT(j1, j5, H15);
             H33 = fmaT(j3, j3, H33); H34 = fmaT(j3, j4, H34); H35 = fmaT(j3, j5, H35);
             H45 = fmaT(j4, j5, H45); H55 = fmaT(j5, j5, H55);
-            S0 = fmaT(j0, rw, S0); S1 = fmaT(j1, rw, S1); S2 = fmaT(rw, rw, S2);
-            S3 = fmaT(j3, rw, S3); S4 = fmaT(j4, rw, S4); S5 = fmaT(j5, rw, S5);
-            G0 = fmaT(j0, je, G0); G1 = fmaT(j1, je, G1); G2 = fmaT(rw, je, G2);
+            S0 = fmaT(j0, wr, S0); S1 = fmaT(j1, wr, S1); S2 = fmaT(wr, wr, S2);
+            S3 = fmaT(j3, wr, S3); S4 = fmaT(j4, wr, S4); S5 = fmaT(j5, wr, S5);
+            G0 = fmaT(j0, je, G0); G1 = fmaT(j1, je, G1); G2 = fmaT(wr, je, G2);
             G3 = fmaT(j3, je, G3); G4 = fmaT(j4, je, G4); G5 = fmaT(j5, je, G5);
         });
         // Normal equations of Eq. (10) for the parameters (theta_x, theta_y, t_z, A, B, C):
         // J2 = -1, and J3, J5 carry a factor 1/2 (de/dA = qx^2/2, de/dC = qy^2/2).
         // H44 = sum w qx^2 qy^2 = 4 * (H35 scaled) -- same sum as sx^2 * sy^2.
-        Real Hm[6][6], gv[6];
-        Hm[0][0] = H00; Hm[0][1] = H01; Hm[0][2] = -S0; Hm[0][3] = Real(0.5) * H03; Hm[0][4] = H04; Hm[0][5] = Real(0.5) * H05;
-        Hm[1][1] = H11; Hm[1][2] = -S1; Hm[1][3] = Real(0.5) * H13; Hm[1][4] = H14; Hm[1][5] = Real(0.5) * H15;
-        Hm[2][2] = S2; Hm[2][3] = Real(-0.5) * S3; Hm[2][4] = -S4; Hm[2][5] = Real(-0.5) * S5;
-        Hm[3][3] = Real(0.25) * H33; Hm[3][4] = Real(0.5) * H34; Hm[3][5] = Real(0.25) * H35;
-        Hm[4][4] = H35; Hm[4][5] = Real(0.5) * H45;
-        Hm[5][5] = Real(0.25) * H55;
-        gv[0] = G0; gv[1] = G1; gv[2] = -G2; gv[3] = Real(0.5) * G3; gv[4] = G4; gv[5] = Real(0.5) * G5;
+        Acc Hm[6][6], gv[6];
+        Hm[0][0] = H00; Hm[0][1] = H01; Hm[0][2] = -S0; Hm[0][3] = Acc(0.5) * H03; Hm[0][4] = H04; Hm[0][5] = Acc(0.5) * H05;
+        Hm[1][1] = H11; Hm[1][2] = -S1; Hm[1][3] = Acc(0.5) * H13; Hm[1][4] = H14; Hm[1][5] = Acc(0.5) * H15;
+        Hm[2][2] = S2; Hm[2][3] = Acc(-0.5) * S3; Hm[2][4] = -S4; Hm[2][5] = Acc(-0.5) * S5;
+        Hm[3][3] = Acc(0.25) * H33; Hm[3][4] = Acc(0.5) * H34; Hm[3][5] = Acc(0.25) * H35;
+        Hm[4][4] = H35; Hm[4][5] = Acc(0.5) * H45;
+        Hm[5][5] = Acc(0.25) * H55;
+        gv[0] = G0; gv[1] = G1; gv[2] = -G2; gv[3] = Acc(0.5) * G3; gv[4] = G4; gv[5] = Acc(0.5) * G5;
 
         // Jacobi equilibration, then LDL^T with pivots dp[j] of the unit-diagonal matrix.
-        Real dsc[6];
+        Acc dsc[6];
         bool singular = false;
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            singular |= !(Hm[i][i] > Real(0));
-            dsc[i] = Hm[i][i] > Real(0) ? rsqrtT(Hm[i][i]) : Real(0);
+            singular |= !(Hm[i][i] > Acc(0));
+            dsc[i] = Hm[i][i] > Acc(0) ? rsqrtT(Hm[i][i]) : Acc(0);
         }
-        Real L[6][6], dp[6];
+        Acc L[6][6], dp[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            Real dj = Real(1);   // equilibrated diagonal
+            Acc dj = Acc(1);   // equilibrated diagonal
 #pragma unroll
             for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k] * dp[k];
             dp[j] = dj;
-            const Real idj = dj > Real(0) ? Real(1) / dj : Real(0);
+            const Acc idj = dj > Acc(0) ? Acc(1) / dj : Acc(0);
 #pragma unroll
             for (int i = j + 1; i < 6; ++i) {
-                Real sij = dsc[i] * dsc[j] * Hm[j][i];
+                Acc sij = dsc[i] * dsc[j] * Hm[j][i];
 #pragma unroll
                 for (int k = 0; k < j; ++k) sij -= L[i][k] * L[j][k] * dp[k];
                 L[i][j] = sij * idj;
             }
         }
-        Real pmin = dp[0], pmax = dp[0];
+        Acc pmin = dp[0], pmax = dp[0];
 #pragma unroll
         for (int j = 1; j < 6; ++j) { pmin = fmin(pmin, dp[j]); pmax = fmax(pmax, dp[j]); }
         // FP64 reads its pivots literally, like the oracle's Cholesky test (1e-12 of the
         // diagonal); FP32 treats anything beyond its accuracy as a reason to recompute.
-        if (singular || !(pmin > Real(1e-12))) {
+        if (singular || !(pmin > Acc(1e-12))) {
             if (fp32) out.flags = kFlagIll;
             return out;
         }
         kappa_max = fmax(kappa_max, pmax / pmin);
-        Real y[6], b[6];
+        Acc y[6], b[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            Real sy = dsc[i] * gv[i];
+            Acc sy = dsc[i] * gv[i];
 #pragma unroll
             for (int k = 0; k < i; ++k) sy -= L[i][k] * y[k];
             y[i] = sy;
         }
 #pragma unroll
         for (int i = 5; i >= 0; --i) {
-            Real sb = y[i] / dp[i];
+            Acc sb = y[i] / dp[i];
 #pragma unroll
             for (int k = i + 1; k < 6; ++k) sb -= L[k][i] * b[k];
             b[i] = sb;
         }
-        Real step = 0;
+        Acc step = 0;
 #pragma unroll
         for (int i = 0; i < 6; ++i) { b[i] *= dsc[i]; step = fmax(step, fabs(b[i])); }
         last_step = step;
@@ -326,7 +331,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
         // Update (Section 3.2.3): R <- Exp([(-b0, -b1, 0)]x) R (exact Rodrigues),
         // t_z -= b2, A -= b3, B -= b4, C -= b5.
         {
-            const Real w0 = -b[0], w1 = -b[1];
+            const Real w0 = Real(-b[0]), w1 = Real(-b[1]);
             const Real th2 = w0 * w0 + w1 * w1;
             Real st = Real(1), c1 = Real(0.5);
             if (th2 > Real(0)) {
@@ -350,10 +355,10 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
 #pragma unroll
                 for (int j = 0; j < 3; ++j) R[i][j] = Rn[i][j];
         }
-        tz -= b[2];
-        A -= b[3];
-        B -= b[4];
-        C -= b[5];
+        tz -= Real(b[2]);
+        A -= Real(b[3]);
+        B -= Real(b[4]);
+        C -= Real(b[5]);
     }
 
     if (want_residual) {
@@ -395,7 +400,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
     out.n[1] = R[2][1];
     out.n[2] = R[2][2];
     out.flags = kFlagValid | (fp32 ? 0 : kFlagFp64);
-    if (fp32 && (ill || !(kappa_max <= Real(d.cond_max)) || !(last_step <= Real(d.step_max))))
+    if (fp32 && (ill || !(kappa_max <= Acc(d.cond_max)) || !(last_step <= Acc(d.step_max))))
         out.flags |= kFlagIll;
     return out;
 }
@@ -507,37 +512,48 @@ __global__ __launch_bounds__(64) void refit_blocks_f64(FitDesc d, const uint32_t
 
 template <int R>
 hipError_t launch_radius(const FitDesc& d, uint32_t* entries, uint64_t* masks, uint32_t* counts,
-                         hipStream_t st) {
+                         hipStream_t st, hipEvent_t* ev) {
     const int halo = R > d.normal_radius ? R : d.normal_radius;
     const uint32_t tiles_x = (d.width + kTileW - 1) / kTileW;
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if (d.precision == 2) {
         constexpr int TH = 4;
         const size_t lds = sizeof(float2) * (kTileW + 2 * halo) * (TH + 2 * halo);
         dim3 grid(tiles_x, (d.height + TH - 1) / TH);
         hipLaunchKernelGGL((fit_tile<double, R, TH>), grid, dim3(kTileW * TH), lds, st, d, entries,
                            masks, counts);
-        return hipGetLastError();
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+        return hipSuccess;
     }
     constexpr int TH = 16;
     const size_t lds = sizeof(float2) * (kTileW + 2 * halo) * (TH + 2 * halo);
     dim3 grid(tiles_x, (d.height + TH - 1) / TH);
     hipLaunchKernelGGL((fit_tile<float, R, TH>), grid, dim3(kTileW * TH), lds, st, d, entries, masks,
                        counts);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || d.precision != 0) return e;
-    // One workgroup per listed block in the worst case, capped; each loops over entries.
-    const uint32_t blocks = tiles_x * grid.y * (TH / 4);
-    const uint32_t nwg = blocks < 8192u ? blocks : 8192u;
-    const size_t lds64 = sizeof(float2) * (kTileW + 2 * halo) * (4 + 2 * halo);
-    hipLaunchKernelGGL(refit_blocks_f64<R>, dim3(nwg), dim3(64), lds64, st, d, entries, masks, counts);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+    if (d.precision == 0) {
+        // One workgroup per listed block in the worst case, capped; each loops over entries.
+        const uint32_t blocks = tiles_x * grid.y * (TH / 4);
+        const uint32_t nwg = blocks < 8192u ? blocks : 8192u;
+        const size_t lds64 = sizeof(float2) * (kTileW + 2 * halo) * (4 + 2 * halo);
+        hipLaunchKernelGGL(refit_blocks_f64<R>, dim3(nwg), dim3(64), lds64, st, d, entries, masks,
+                           counts);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 template <int... Rs>
 hipError_t dispatch_radius(int r, const FitDesc& d, uint32_t* entries, uint64_t* masks,
-                           uint32_t* counts, hipStream_t st, std::integer_sequence<int, Rs...>) {
+                           uint32_t* counts, hipStream_t st, hipEvent_t* ev,
+                           std::integer_sequence<int, Rs...>) {
     hipError_t e = hipErrorInvalidValue;
-    (void)((r == Rs + 1 ? (e = launch_radius<Rs + 1>(d, entries, masks, counts, st), true) : false) || ...);
+    (void)((r == Rs + 1 ? (e = launch_radius<Rs + 1>(d, entries, masks, counts, st, ev), true) : false) || ...);
     return e;
 }
 
@@ -550,13 +566,13 @@ int64_t refit_capacity(int width, int height) {
 }
 
 hipError_t launch_fit(const FitDesc& d, uint32_t* entries, uint64_t* masks, uint32_t* counts,
-                      hipStream_t stream) {
+                      hipStream_t stream, hipEvent_t* events) {
     if (d.precision != 2) {
         hipLaunchKernelGGL(zero_counts, dim3(1), dim3(1), 0, stream, counts);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return dispatch_radius(d.radius, d, entries, masks, counts, stream,
+    return dispatch_radius(d.radius, d, entries, masks, counts, stream, events,
                            std::make_integer_sequence<int, kMaxRadius>{});
 }
 

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "fit_internal.h"
 #include "qcurv.h"
@@ -19,6 +20,10 @@ struct qc_context {
     int64_t capacity = 0;
     hipStream_t last_stream = nullptr;
     int last_precision = 0;
+    // timing: recorded event triples not yet read, and the sums of those already read
+    bool timing = false;
+    std::vector<hipEvent_t> pending;
+    qc_timing sums{};
 };
 
 namespace {
@@ -106,7 +111,7 @@ void qc_params_default(qc_params* p) {
     p->depth_scale = 1e-3f;
     p->precision = QC_PREC_MIXED;
     p->cond_max = 30.f;
-    p->step_max = 1e-2f;
+    p->step_max = 1e-1f;
 }
 
 qc_status qc_create(qc_context** out, int device) {
@@ -140,6 +145,7 @@ qc_status qc_destroy(qc_context* ctx) {
     if (ctx->refit_entries) (void)hipFree(ctx->refit_entries);
     if (ctx->refit_masks) (void)hipFree(ctx->refit_masks);
     if (ctx->refit_counts) (void)hipFree(ctx->refit_counts);
+    for (hipEvent_t ev : ctx->pending) (void)hipEventDestroy(ev);
     delete ctx;
     return QC_OK;
 }
@@ -181,8 +187,14 @@ qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params
     d.residual = out->residual;
     d.flags = out->flags;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((e = qc::launch_fit(d, ctx->refit_entries, ctx->refit_masks, ctx->refit_counts, s)) !=
-        hipSuccess)
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (ctx->timing) {
+        for (auto& x : ev)
+            if ((e = hipEventCreate(&x)) != hipSuccess) return hip_fail(ctx, e);
+        ctx->pending.insert(ctx->pending.end(), ev, ev + 3);
+    }
+    if ((e = qc::launch_fit(d, ctx->refit_entries, ctx->refit_masks, ctx->refit_counts, s,
+                            ctx->timing ? ev : nullptr)) != hipSuccess)
         return hip_fail(ctx, e);
     ctx->last_stream = s;
     ctx->last_precision = params->precision;
@@ -201,6 +213,37 @@ qc_status qc_last_refit_count(qc_context* ctx, uint32_t* count) {
         return hip_fail(ctx, e);
     *count = counts[1];
     return QC_OK;
+}
+
+qc_status qc_set_timing(qc_context* ctx, int enable) {
+    if (!ctx) return QC_ERR_INVALID_ARG;
+    ctx->timing = enable != 0;
+    return QC_OK;
+}
+
+qc_status qc_get_timing(qc_context* ctx, qc_timing* out, int reset) {
+    if (!ctx || !out) return QC_ERR_INVALID_ARG;
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
+    qc_status st = QC_OK;
+    for (size_t i = 0; i + 2 < ctx->pending.size(); i += 3) {
+        hipEvent_t* ev = &ctx->pending[i];
+        float a = 0.f, b = 0.f;
+        if ((e = hipEventSynchronize(ev[2])) != hipSuccess ||
+            (e = hipEventElapsedTime(&a, ev[0], ev[1])) != hipSuccess ||
+            (e = hipEventElapsedTime(&b, ev[1], ev[2])) != hipSuccess) {
+            st = hip_fail(ctx, e);
+        } else {
+            ctx->sums.calls += 1;
+            ctx->sums.fit_ms += a;
+            ctx->sums.refit_ms += b;
+        }
+        for (int j = 0; j < 3; ++j) (void)hipEventDestroy(ev[j]);
+    }
+    ctx->pending.clear();
+    *out = ctx->sums;
+    if (reset) ctx->sums = qc_timing{};
+    return st;
 }
 
 int qc_last_hip_error(qc_context* ctx) { return ctx ? ctx->last_hip_error : 0; }
