@@ -94,6 +94,151 @@ def cpu_baseline(frame: np.ndarray, cam, budget_s: float = 10.0) -> dict:
             "sample": f"{runs} full 640x480 u16 frames (r=7, T=5), FP64 C + OpenMP, {el:.1f} s"}
 
 
+_POOL = {}
+
+
+def sensor_pool(per_kind: int = 3) -> dict:
+    """Rendered u16 frames per sensor kind (ToF 512x424, VGA, 720p), shared by the batched
+    and served measurements."""
+    from paper_1707_00385_amd import scenes
+    if not _POOL:
+        for kind in ("tof", "vga", "hd"):
+            for j in range(per_kind):
+                sc = scenes.sensor_frame(kind, seed_frame=j)
+                _POOL[(kind, j)] = (sc.depth_u16(), sc.camera)
+    return _POOL
+
+
+def measure_served(ctx, duration_s: float = 4.0, fps: float = 240.0, sensors: int = 6) -> dict:
+    """The serving form on a seeded Poisson trace (sensors with fixed resolutions, per-frame
+    window radius 3..11, T = 5) and in a saturating run (the whole trace queued at once),
+    against the plain path (one qc_fit per frame in arrival order, one frame in flight).
+    Latency is completion time minus arrival time."""
+    import threading
+    import torch
+    from paper_1707_00385_amd import scenes
+    from paper_1707_00385_amd.api import Server, make_outputs, make_params, upload_depth
+    pool = sensor_pool()
+    trace = scenes.poisson_trace(sensors, fps, duration_s, seed=0)
+    params = {r: make_params(radius=r, iterations=5) for r in range(3, 12)}
+    frames = [pool[(e["kind"], i % 3)] for i, e in enumerate(trace)]
+    total_px = sum(d.size for d, _ in frames)
+
+    def served(realtime: bool) -> dict:
+        srv = Server(ctx, memory_budget=2 << 30, max_batch=32, max_in_flight=2)
+        lat, t_first, t_last = [], None, 0.0
+        arrivals = {}
+        base = time.perf_counter()
+        state = {"fed": 0}
+
+        def feed():
+            for i, e in enumerate(trace):
+                if realtime:
+                    delay = base + e["t"] - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                d, cam = frames[i]
+                while True:
+                    arrivals[i] = time.perf_counter()
+                    t = srv.submit(d, "u16", (cam.fx, cam.fy, cam.cx, cam.cy), params[e["radius"]], tag=i)
+                    if t is not None:
+                        break
+                    time.sleep(0.0002)
+                state["fed"] += 1
+
+        th = threading.Thread(target=feed)
+        th.start()
+        done = 0
+        while done < len(trace):
+            for c in srv.poll(64, wait_us=2000):
+                now = time.perf_counter()
+                lat.append(1e3 * (now - arrivals[c.tag]))
+                t_last = now
+                srv.release(c.ticket)
+                done += 1
+        th.join()
+        st = srv.stats()
+        srv.close()
+        span = t_last - base
+        return {"pixels_per_s": round(total_px / span, 1), "frames": len(trace),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3), "batches": st["batches"],
+                "wall_s": round(span, 3)}
+
+    def plain(realtime: bool) -> dict:
+        lat = []
+        outs = {}
+        base = time.perf_counter()
+        for i, e in enumerate(trace):
+            if realtime:
+                delay = base + e["t"] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            arrival = base + e["t"] if realtime else base
+            d, cam = frames[i]
+            t = upload_depth(d, "u16")
+            key = d.shape
+            if key not in outs:
+                outs[key] = make_outputs(d.shape[0], d.shape[1], t.device, flags=False)
+            ctx.fit(t, (cam.fx, cam.fy, cam.cx, cam.cy), params=params[e["radius"]], out=outs[key])
+            torch.cuda.synchronize()
+            lat.append(1e3 * (time.perf_counter() - arrival))
+        span = time.perf_counter() - base
+        return {"pixels_per_s": round(total_px / span, 1), "frames": len(trace),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3), "wall_s": round(span, 3)}
+
+    plain(False)   # warm-up of every radius variant
+    res = {"trace": f"{sensors} sensors, Poisson arrivals {fps:.0f} frames/s aggregate over "
+                    f"{duration_s:.0f} s (seeded), 512x424 ToF / 640x480 / 1280x720 u16, "
+                    f"r in 3..11, T=5, {len(trace)} frames",
+           "served_realtime": served(True), "plain_realtime": plain(True),
+           "served_saturated": served(False), "plain_saturated": plain(False)}
+    return res
+
+
+def measure_batched(ctx, reps: int = 5) -> dict:
+    """The batched form: 64 frames in equal thirds of 512x424 ToF-like, 640x480 and
+    1280x720 depth, window radius from {3, 5, 7, 11}, iterations from {3, 5} (seeded), fitted
+    by one qc_fit_batch call (persistent launches replayed from a graph) and, for
+    comparison, by 64 qc_fit calls.  Three rendered frames per sensor kind are shared by the
+    64 items; every item has its own outputs."""
+    import torch
+    from paper_1707_00385_amd import scenes
+    from paper_1707_00385_amd.api import make_outputs, make_params, upload_depth
+    mix = scenes.batch_mix(64, seed=0)
+    pool = {k: (upload_depth(d, "u16"), cam) for k, (d, cam) in sensor_pool().items()}
+    jobs, pixels, flops = [], 0, 0.0
+    for i, m in enumerate(mix):
+        t, cam = pool[(m["kind"], i % 3)]
+        p = make_params(radius=m["radius"], iterations=m["iterations"])
+        o = make_outputs(t.shape[0], t.shape[1], t.device, flags=False)
+        jobs.append((t, (cam.fx, cam.fy, cam.cx, cam.cy), p, o))
+        pixels += t.shape[0] * t.shape[1]
+    ctx.fit_batch(jobs)
+    for t, K, p, o in jobs:
+        ctx.fit(t, K, params=p, out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.fit_batch(jobs)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for t, K, p, o in jobs:
+            ctx.fit(t, K, params=p, out=o)
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / reps
+    return {"frames": len(jobs), "pixels_per_batch": pixels,
+            "batched": {"ms_per_batch": round(1e3 * t_batch, 3), "pixels_per_s": round(pixels / t_batch, 1)},
+            "per_frame_launches": {"ms_per_batch": round(1e3 * t_single, 3),
+                                   "pixels_per_s": round(pixels / t_single, 1)},
+            "speedup": round(t_single / t_batch, 3),
+            "mix": "64 frames: 1/3 each 512x424 ToF (sigma=1e-3 Z), 640x480 and 1280x720 "
+                   "Kinect-like u16; r in {3,5,7,11}, T in {3,5}, seeded"}
+
+
 def copy_calibration(nbytes: int) -> int:
     """Ten device-to-device copies of a known size: the HBM read/write counters of these
     dispatches give the scale factor between counter readings and bytes moved."""
@@ -115,6 +260,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--latency-frames", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 10 plain device copies of BYTES bytes (calibrates the "
@@ -213,6 +360,16 @@ def main() -> int:
         "refit_fraction": round(float(np.mean(refits)) / (WIDTH * HEIGHT), 5),
         "roofline": roofline,
     }
+    if not args.no_batched and args.precision != "fp64":
+        result["batched_form"] = measure_batched(ctx)
+    if not args.no_served and args.precision != "fp64":
+        sv = measure_served(ctx)
+        result["served_form"] = sv
+        result["served_vs_plain"] = {
+            "saturated_throughput_ratio": round(sv["served_saturated"]["pixels_per_s"] /
+                                                sv["plain_saturated"]["pixels_per_s"], 3),
+            "realtime_p99_ms": {"served": sv["served_realtime"]["p99_ms"],
+                                "plain": sv["plain_realtime"]["p99_ms"]}}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(frames[0], cam)
     print(json.dumps(result), flush=True)

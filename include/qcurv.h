@@ -79,7 +79,12 @@ typedef struct {
     float depth_scale;       /* metres per unit of U16 depth; ignored for F16/F32 */
     int32_t precision;       /* qc_precision */
     float cond_max;          /* MIXED: refit if the equilibrated pivot ratio exceeds this */
-    float step_max;          /* MIXED: refit if the last update's max-norm exceeds this */
+    float step_max;          /* MIXED: refit if the last update exceeds this, measured in
+                                window units: radians, t_z / h_w and h_w * (A, B, C), with
+                                h_w = r Z / fx the window half-extent at the pixel */
+    int32_t tile_width;      /* FP32 pass tile: 8, 16, 32 or 64 pixels wide (256 pixels);
+                                0 = the width qc_tune recorded for this frame size, radius
+                                and iteration count, else 16.  Results do not depend on it. */
 } qc_params;
 
 typedef struct {
@@ -101,7 +106,7 @@ typedef struct {
 typedef struct qc_context qc_context;
 
 /* Defaults: r = 7, r_n = 3, T = 5, k = 1e-5 m^2, depth_scale = 1e-3, MIXED,
- * cond_max = 30, step_max = 0.1. */
+ * cond_max = 30, step_max = 0.1, tile_width = 0. */
 void qc_params_default(qc_params* params);
 
 /* Creates a context bound to HIP device `device`.  *ctx receives the handle. */
@@ -115,6 +120,108 @@ qc_status qc_destroy(qc_context* ctx);
  * one context must be ordered on one stream. */
 qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params,
                  const qc_output* out, void* stream);
+
+/* One frame of a batch: its depth, parameters and outputs. */
+typedef struct {
+    qc_frame frame;
+    qc_params params;
+    qc_output out;
+} qc_batch_item;
+
+#define QC_MAX_BATCH 256
+
+/* Fits up to QC_MAX_BATCH frames of any sizes, window radii and iteration counts with one
+ * persistent FP32 launch over all their tiles and one persistent FP64 recomputation
+ * launch (MIXED), replayed from a HIP graph the context captures once.  Each item's
+ * outputs equal, bit for bit, those of qc_fit on the same item.  All items must use the
+ * same precision, MIXED or FP32 (FP64 frames go through qc_fit).  At most two batches
+ * are in flight per context; a third call first waits for the oldest.  Asynchronous on
+ * `stream`; the items array itself may be reused as soon as the call returns. */
+qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, void* stream);
+
+/* Autotuning of the FP32 tile shape: runs qc_fit on `frame` with each tile width (8, 16,
+ * 32, 64), `reps` times each, timed with HIP events on `stream`, writing into `out`
+ * (whose contents are then undefined), and records the fastest width for frames of that
+ * size, radius and iteration count; `tile_width` (may be NULL) receives it.  Synchronous. */
+qc_status qc_tune(qc_context* ctx, const qc_frame* frame, const qc_params* params,
+                  const qc_output* out, int32_t reps, void* stream, int32_t* tile_width);
+
+/* Saves / loads the recorded tile widths as text lines "width height radius iterations
+ * tile_width" (load merges into the context's table). */
+qc_status qc_tune_save(qc_context* ctx, const char* path);
+qc_status qc_tune_load(qc_context* ctx, const char* path);
+
+/* ------------------------------------------------------------------------------------
+ * Serving: frames from several producers are admitted by device memory, uploaded, and
+ * fitted in batches (qc_fit_batch) as they arrive: a frame that arrives while batches run
+ * joins the next batch, and up to two batches overlap on the GPU.  Results stay in device
+ * memory until released.  A server owns its context from creation to destruction: the
+ * context must not be used by the caller meanwhile.
+ * ---------------------------------------------------------------------------------- */
+typedef struct qc_server qc_server;
+
+#define QC_OUT_NORMAL 1
+#define QC_OUT_RESIDUAL 2
+#define QC_OUT_FLAGS 4
+
+typedef struct {
+    size_t memory_budget;    /* device bytes for resident depth + outputs, >= one frame */
+    int32_t max_batch;       /* frames per batch, 1..QC_MAX_BATCH */
+    int32_t max_in_flight;   /* batches on the GPU at once, 1 or 2 */
+    int32_t outputs;         /* QC_OUT_* bits; k1 and k2 are always produced */
+    size_t staging_budget;   /* pinned host bytes holding submitted, not yet uploaded frames */
+} qc_server_config;
+
+typedef struct {
+    const void* depth;       /* host pointer; copied before qc_server_submit returns */
+    int32_t format;          /* qc_depth_format */
+    int32_t width, height;
+    int64_t pitch_bytes;
+    qc_intrinsics K;
+    qc_params params;        /* MIXED or FP32 */
+    uint64_t tag;            /* returned with the completion */
+} qc_request;
+
+typedef struct {
+    uint64_t ticket;
+    uint64_t tag;
+    int32_t status;          /* qc_status of the request */
+    int32_t width, height;
+    int64_t t_submit_ns;     /* steady-clock times of submission and completion */
+    int64_t t_done_ns;
+    const float* k1;         /* device pointers, valid until qc_server_release(ticket) */
+    const float* k2;
+    const float* normal;
+    const float* residual;
+    const uint8_t* flags;
+} qc_completion;
+
+/* Starts a server on `ctx` (its device) with the given configuration. */
+qc_status qc_server_create(qc_context* ctx, const qc_server_config* config, qc_server** out);
+
+/* Queues one frame; *ticket identifies it.  Returns QC_ERR_BUSY when the pinned staging
+ * cannot hold the frame now (retry after polling), QC_ERR_INVALID_ARG for a frame that
+ * could never be admitted (larger than the memory budget). */
+qc_status qc_server_submit(qc_server* server, const qc_request* request, uint64_t* ticket);
+
+/* Returns up to `max` completions not yet returned, waiting up to `wait_us` microseconds
+ * for the first one; *n receives the count. */
+qc_status qc_server_poll(qc_server* server, qc_completion* out, int32_t max, int32_t* n,
+                         int64_t wait_us);
+
+/* Frees a completed request's device buffers. */
+qc_status qc_server_release(qc_server* server, uint64_t ticket);
+
+/* Counters: submitted, completed, queued (not yet on the GPU), bytes of device memory in
+ * use, batches launched. */
+typedef struct {
+    uint64_t submitted, completed, queued, batches;
+    size_t device_bytes_in_use;
+} qc_server_stats;
+qc_status qc_server_get_stats(qc_server* server, qc_server_stats* out);
+
+/* Waits for all submitted frames, stops the server and frees its memory. */
+qc_status qc_server_destroy(qc_server* server);
 
 /* Number of pixels recomputed in FP64 by the most recent qc_fit on this context
  * (MIXED), or flagged (FP32).  Synchronises with that call's stream. */

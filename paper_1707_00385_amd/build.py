@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libqcurv.so")
 
-SOURCES = ["fit_kernels.hip", "qcurv_api.cpp"]
+SOURCES = ["fit_kernels.hip", "qcurv_api.cpp", "serve.cpp"]
 
 # Packed FP32 instructions are disabled: the compiler would otherwise form them from
 # scalar float code.  fp-contract is off so that every fused multiply-add is the one

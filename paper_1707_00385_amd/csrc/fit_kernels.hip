@@ -11,11 +11,11 @@
 //    native units and s metres per unit, p' = P_i - P_c = s * G0 * m with
 //    m = ((u_i-u_c) D_i, (v_i-v_c) D_i, D_i - D_c), which is exact for U16 and F16 input,
 //    and G0 = [[1/fx, 0, (u_c-cx)/fx], [0, 1/fy, (v_c-cy)/fy], [0, 0, 1]].
-//  * Lengths are measured in units of h = r Z_c / fx (the window half-extent), so the
-//    patch coefficients become A h, B h, C h, t_z / h and k / h^2; Gauss-Newton is
+//  * Lengths are measured in units of h = sqrt(k), so the patch coefficients become A h,
+//    B h, C h, t_z / h and the weight of Eq. (11) becomes 1/(1 + e^2); Gauss-Newton is
 //    invariant under this rescaling, so the iterates are the same.
 //  * Each neighbour contributes sqrt(w) J to the normal equations (H = sum (sqrt w J)
-//    (sqrt w J)^T, g = sum (sqrt w J)(sqrt w e)), with w = 1/(k + e^2): the factor k of
+//    (sqrt w J)^T, g = sum (sqrt w J)(sqrt w e)), with w = 1/(1 + e^2): the factor k of
 //    Eq. (11) cancels in (J^T W J)^{-1} J^T W e.
 //  * The 6x6 solve is Jacobi-equilibrated LDL^T; the pivot ratio estimates the
 //    condition number that decides the FP64 recomputation.
@@ -34,6 +34,10 @@ namespace {
 constexpr int kMaxRadius = 18;
 constexpr uint8_t kFlagValid = 1, kFlagFp64 = 2, kFlagIll = 4;
 constexpr int kTileW = 16;
+
+#ifndef QC_F32_WAVES_PER_EU
+#define QC_F32_WAVES_PER_EU 4
+#endif
 
 // ---------------------------------------------------------------------------- scalars
 template <typename T> __device__ __forceinline__ T fmaT(T a, T b, T c);
@@ -56,15 +60,17 @@ __device__ __forceinline__ float load_sample(const FitDesc& d, int x, int y) {
     return reinterpret_cast<const float*>(row)[x];
 }
 
-// (D, pen): D = depth in native units, pen = 0 for a valid sample and +inf for a
-// missing one (outside the image, zero or non-finite).  pen is added to the weight's
-// denominator so a missing neighbour gets weight exactly 0 without a branch.
+// (D, c): D = depth in native units; c = 1 for a valid sample and +inf for a missing one
+// (outside the image, zero or non-finite).  With lengths in units of sqrt(k) the weight
+// of Eq. (11) is 1/(c + e^2): a missing neighbour gets weight exactly 0 without a branch.
 __device__ __forceinline__ float2 sample_or_missing(const FitDesc& d, int x, int y) {
     if (x < 0 || y < 0 || x >= d.width || y >= d.height) return make_float2(0.f, INFINITY);
     float z = load_sample(d, x, y);
     bool ok = z > 0.f && z <= 3.0e38f;   // excludes 0, negatives, inf and NaN
-    return make_float2(ok ? z : 0.f, ok ? 0.f : INFINITY);
+    return make_float2(ok ? z : 0.f, ok ? 1.f : INFINITY);
 }
+
+__device__ __forceinline__ bool present(float2 t) { return t.y == 1.f; }
 
 // Neighbourhood accessors.  row(dv)[du] is the (D, pen) pair of pixel (u+du, v+dv).
 struct LdsRow {
@@ -76,17 +82,6 @@ struct LdsSource {
     int pitch;              // entries per LDS row
     __device__ __forceinline__ LdsRow row(int dv) const { return LdsRow{centre + dv * pitch}; }
 };
-struct GlobalRow {
-    const FitDesc* d;
-    int u, y;
-    __device__ __forceinline__ float2 operator[](int du) const { return sample_or_missing(*d, u + du, y); }
-};
-struct GlobalSource {
-    const FitDesc* d;
-    int u, v;
-    __device__ __forceinline__ GlobalRow row(int dv) const { return GlobalRow{d, u, v + dv}; }
-};
-
 // ---------------------------------------------------------------------------- one pixel
 template <typename Real>
 struct PixelFit {
@@ -97,34 +92,59 @@ struct PixelFit {
 // Per-pixel geometry: p'/h = G m (see the header comment).
 template <typename Real>
 struct Geometry {
-    Real Dc, g00, g02, g11, g12, g22, h, ih, kt;
+    Real Dc, g00, g02, g11, g12, g22, h, ih;
 };
 
-// Loops over the window rows -R..R; RC > 0 fixes R at compile time.  A row is fully
+// A pixel's fit may be shared by NP consecutive lanes: lane `part` takes the window rows
+// dv = -r + part, -r + part + NP, ..., and sum() adds a value over the group by an xor
+// butterfly, which leaves every lane of the group with the same bits (the additions are
+// the same pairs in the same order up to commutation).  NP = 1 is one lane per pixel.
+template <int NP>
+struct LaneGroup {
+    int part;
+    template <typename T>
+    __device__ __forceinline__ T sum(T x) const {
+        if constexpr (NP > 1) {
+#pragma unroll
+            for (int m = 1; m < NP; m <<= 1) x += __shfl_xor(x, m);
+        }
+        return x;
+    }
+};
+
+// Loops over this lane's window rows; RC > 0 fixes R at compile time.  A row is fully
 // unrolled for FP32 (U = 0); FP64 keeps it rolled (U = 1) to stay within the register file.
-template <int RC, int U = 0, typename Src, typename F>
-__device__ __forceinline__ void for_window(const Src& src, int radius, F&& f) {
+template <int RC, int U, int NP, typename Src, typename F>
+__device__ __forceinline__ void for_window(const Src& src, int radius, const LaneGroup<NP>& grp,
+                                           F&& f) {
+    const int r = RC > 0 ? RC : radius;
+    const int first = NP > 1 ? -r + grp.part : -r;
     if constexpr (RC > 0 && U == 0) {
-        for (int dv = -RC; dv <= RC; ++dv) {
+        for (int dv = first; dv <= r; dv += NP) {
             auto row = src.row(dv);
 #pragma unroll
             for (int du = -RC; du <= RC; ++du) f(row[du], du, dv);
         }
     } else {
-        const int r = RC > 0 ? RC : radius;
-        for (int dv = -r; dv <= r; ++dv) {
+        // rolled row: the next sample's LDS read is issued before this one is used
+        for (int dv = first; dv <= r; dv += NP) {
             auto row = src.row(dv);
+            float2 cur = row[-r];
 #pragma unroll 1
-            for (int du = -r; du <= r; ++du) f(row[du], du, dv);
+            for (int du = -r; du <= r; ++du) {
+                const float2 nxt = row[du < r ? du + 1 : du];
+                f(cur, du, dv);
+                cur = nxt;
+            }
         }
     }
 }
 
 // The pixel's fit, Section 3.2: initial normal (Eq. (7)), frame set-up, fixed number of
 // re-weighted Gauss-Newton steps (Eqs. (8)-(11)), curvatures, refined normal.
-template <typename Real, int RC, typename Src>
+template <typename Real, int RC, int NP = 1, typename Src>
 __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int v, float Dc_f,
-                                    bool want_residual) {
+                                    bool want_residual, LaneGroup<NP> grp = LaneGroup<NP>{0}) {
     PixelFit<Real> out;
     const Real nan = Real(NAN);
     out.k1 = out.k2 = out.residual = nan;
@@ -139,8 +159,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
     g.Dc = Real(Dc_f);
     const Real s = Real(d.scale);
     const Real fx = Real(d.fx), fy = Real(d.fy);
-    const Real Zc = g.Dc * s;
-    g.h = Real(radius) * Zc / fx;
+    g.h = sqrtT(Real(d.k));
     g.ih = Real(1) / g.h;
     const Real ihs = g.ih * s;
     g.g00 = ihs / fx;
@@ -148,14 +167,13 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
     g.g11 = ihs / fy;
     g.g12 = ihs * ((Real(v) - Real(d.cy)) / fy);
     g.g22 = ihs;
-    g.kt = Real(d.k) * g.ih * g.ih;
 
     // ---- initial normal, Section 3.2.1: regression z = a x + b y over the small window
     //      with mean-centred sums M, v; n0 = (-a, -b, 1) / sqrt(1 + a^2 + b^2)
     const int rn = d.normal_radius;
     Real cnt = 0, mx_ = 0, my_ = 0, mz_ = 0;
-    for_window<0>(src, rn, [&](float2 t, int du, int dv) {
-        const Real ok = t.y == 0.f ? Real(1) : Real(0);
+    for_window<0, 1>(src, rn, grp, [&](float2 t, int du, int dv) {
+        const Real ok = present(t) ? Real(1) : Real(0);
         const Real D = Real(t.x), dD = D - g.Dc;
         const Real px = fmaT(g.g00, Real(du) * D, g.g02 * dD);
         const Real py = fmaT(g.g11, Real(dv) * D, g.g12 * dD);
@@ -165,11 +183,15 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
         my_ = fmaT(ok, py, my_);
         mz_ = fmaT(ok, pz, mz_);
     });
+    cnt = grp.sum(cnt);
+    mx_ = grp.sum(mx_);
+    my_ = grp.sum(my_);
+    mz_ = grp.sum(mz_);
     if (cnt < Real(3)) return out;
     mx_ /= cnt; my_ /= cnt; mz_ /= cnt;
     Real M00 = 0, M01 = 0, M11 = 0, v0 = 0, v1 = 0;
-    for_window<0>(src, rn, [&](float2 t, int du, int dv) {
-        const Real ok = t.y == 0.f ? Real(1) : Real(0);
+    for_window<0, 1>(src, rn, grp, [&](float2 t, int du, int dv) {
+        const Real ok = present(t) ? Real(1) : Real(0);
         const Real D = Real(t.x), dD = D - g.Dc;
         const Real px = fmaT(g.g00, Real(du) * D, g.g02 * dD) - mx_;
         const Real py = fmaT(g.g11, Real(dv) * D, g.g12 * dD) - my_;
@@ -181,6 +203,11 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
         v0 = fmaT(opx, pz, v0);
         v1 = fmaT(opy, pz, v1);
     });
+    M00 = grp.sum(M00);
+    M01 = grp.sum(M01);
+    M11 = grp.sum(M11);
+    v0 = grp.sum(v0);
+    v1 = grp.sum(v1);
     const Real det = M00 * M11 - M01 * M01;
     const Real tr = M00 + M11;
     bool ill = false;
@@ -196,7 +223,9 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
 
     // ---- enough neighbours for six parameters
     Real nfit = 0;
-    for_window<RC, sizeof(Real) == 8>(src, radius, [&](float2 t, int, int) { nfit += t.y == 0.f ? Real(1) : Real(0); });
+    for_window<RC, sizeof(Real) == 8>(src, radius, grp,
+                                      [&](float2 t, int, int) { nfit += present(t) ? Real(1) : Real(0); });
+    nfit = grp.sum(nfit);
     if (nfit < Real(6)) return out;
 
     // ---- frame: smallest rotation taking n0 to e_z; R = I + [w]x + [w]x^2/(1+c),
@@ -210,6 +239,8 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
     }
     Real tz = 0, A = 0, B = 0, C = 0;     // patch coefficients in units of h
     Acc kappa_max = 0, last_step = 0;
+    // window half-extent r Z_c / fx in units of h
+    const Acc hwin = Acc(radius) * Acc(g.Dc) * Acc(s) / Acc(fx) * Acc(g.ih);
 
     for (int it = 0; it < d.iterations; ++it) {
         // R' = R G: maps m straight to the rotated, scaled, centred point s = R p'/h.
@@ -231,19 +262,19 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
         Acc H33 = 0, H34 = 0, H35 = 0, H45 = 0, H55 = 0;
         Acc S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0;
         Acc G0 = 0, G1 = 0, G2 = 0, G3 = 0, G4 = 0, G5 = 0;
-        for_window<RC, sizeof(Real) == 8>(src, radius, [&](float2 t, int du, int dv) {
+        for_window<RC, sizeof(Real) == 8>(src, radius, grp, [&](float2 t, int du, int dv) {
+            // s = R' m with m = (du D, dv D, D - Dc), as (R'x0 du + R'x1 dv) D + R'x2 (D - Dc)
             const Real D = Real(t.x);
             const Real dD = D - g.Dc;
-            const Real mx = Real(du) * D, my = Real(dv) * D;
-            const Real sx = fmaT(Rp[0][0], mx, fmaT(Rp[0][1], my, Rp[0][2] * dD));
-            const Real sy = fmaT(Rp[1][0], mx, fmaT(Rp[1][1], my, Rp[1][2] * dD));
-            const Real sz2 = fmaT(Rp[2][0], mx, fmaT(Rp[2][1], my, Rp[2][2] * dD));
+            const Real fdu = Real(du), fdv = Real(dv);
+            const Real sx = fmaT(fmaT(Rp[0][0], fdu, Rp[0][1] * fdv), D, Rp[0][2] * dD);
+            const Real sy = fmaT(fmaT(Rp[1][0], fdu, Rp[1][1] * fdv), D, Rp[1][2] * dD);
+            const Real sz2 = fmaT(fmaT(Rp[2][0], fdu, Rp[2][1] * fdv), D, Rp[2][2] * dD);
             const Real qz = fmaT(Real(0.5), sz2, tz);
             const Real ap = fmaT(Ah, sx, Bh * sy);          // (A qx + B qy) / 2
             const Real cp = fmaT(Bh, sx, Ch * sy);          // (B qx + C qy) / 2
             const Real e = fmaT(ap, sx, fmaT(cp, sy, -qz)); // Eq. (6): A/2 qx^2 + B qx qy + C/2 qy^2 - qz
-            const Real den = fmaT(e, e, g.kt) + Real(t.y);
-            const Real rw = rsqrtT(den);                    // sqrt of the weight, Eq. (11)
+            const Real rw = rsqrtT(fmaT(e, e, Real(t.y)));  // sqrt of the weight, Eq. (11)
             const Real J0 = -fmaT(cp, sz2, sy);             // de/dtheta_x
             const Real J1 = fmaT(ap, sz2, sx);              // de/dtheta_y
             const Real j0r = rw * J0, j1r = rw * J1;
@@ -262,6 +293,16 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             G0 = fmaT(j0, je, G0); G1 = fmaT(j1, je, G1); G2 = fmaT(wr, je, G2);
             G3 = fmaT(j3, je, G3); G4 = fmaT(j4, je, G4); G5 = fmaT(j5, je, G5);
         });
+        if constexpr (NP > 1) {
+            H00 = grp.sum(H00); H01 = grp.sum(H01); H03 = grp.sum(H03); H04 = grp.sum(H04);
+            H05 = grp.sum(H05); H11 = grp.sum(H11); H13 = grp.sum(H13); H14 = grp.sum(H14);
+            H15 = grp.sum(H15); H33 = grp.sum(H33); H34 = grp.sum(H34); H35 = grp.sum(H35);
+            H45 = grp.sum(H45); H55 = grp.sum(H55);
+            S0 = grp.sum(S0); S1 = grp.sum(S1); S2 = grp.sum(S2);
+            S3 = grp.sum(S3); S4 = grp.sum(S4); S5 = grp.sum(S5);
+            G0 = grp.sum(G0); G1 = grp.sum(G1); G2 = grp.sum(G2);
+            G3 = grp.sum(G3); G4 = grp.sum(G4); G5 = grp.sum(G5);
+        }
         // Normal equations of Eq. (10) for the parameters (theta_x, theta_y, t_z, A, B, C):
         // J2 = -1, and J3, J5 carry a factor 1/2 (de/dA = qx^2/2, de/dC = qy^2/2).
         // H44 = sum w qx^2 qy^2 = 4 * (H35 scaled) -- same sum as sx^2 * sy^2.
@@ -323,10 +364,12 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             for (int k = i + 1; k < 6; ++k) sb -= L[k][i] * b[k];
             b[i] = sb;
         }
-        Acc step = 0;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) { b[i] *= dsc[i]; step = fmax(step, fabs(b[i])); }
-        last_step = step;
+        for (int i = 0; i < 6; ++i) b[i] *= dsc[i];
+        // Size of the update in window units (angles in radians, t_z in window
+        // half-extents, curvatures times the half-extent): how far from converged.
+        last_step = fmax(fmax(fabs(b[0]), fabs(b[1])),
+                         fmax(fabs(b[2]) / hwin, hwin * fmax(fmax(fabs(b[3]), fabs(b[4])), fabs(b[5]))));
 
         // Update (Section 3.2.3): R <- Exp([(-b0, -b1, 0)]x) R (exact Rodrigues),
         // t_z -= b2, A -= b3, B -= b4, C -= b5.
@@ -372,7 +415,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
         }
         const Real Ah = Real(0.5) * A, Bh = Real(0.5) * B, Ch = Real(0.5) * C;
         Real sw = 0, swe = 0;
-        for_window<RC, sizeof(Real) == 8>(src, radius, [&](float2 t, int du, int dv) {
+        for_window<RC, sizeof(Real) == 8>(src, radius, grp, [&](float2 t, int du, int dv) {
             const Real D = Real(t.x), dD = D - g.Dc;
             const Real mx = Real(du) * D, my = Real(dv) * D;
             const Real sx = fmaT(Rp[0][0], mx, fmaT(Rp[0][1], my, Rp[0][2] * dD));
@@ -381,11 +424,13 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             const Real qz = sz + tz;
             const Real ap = fmaT(Ah, sx, Bh * sy), cp = fmaT(Bh, sx, Ch * sy);
             const Real e = fmaT(ap, sx, fmaT(cp, sy, -qz));
-            const Real rw = rsqrtT(fmaT(e, e, g.kt) + Real(t.y));
+            const Real rw = rsqrtT(fmaT(e, e, Real(t.y)));
             const Real w = rw * rw;
             sw += w;
             swe = fmaT(w * e, e, swe);
         });
+        sw = grp.sum(sw);
+        swe = grp.sum(swe);
         out.residual = g.h * sqrtT(swe / sw);
     }
 
@@ -419,14 +464,21 @@ __device__ __forceinline__ void store_pixel(const FitDesc& d, int64_t idx, const
 }
 
 // ---------------------------------------------------------------------------- kernels
-// counts[0]: entries in the recomputation list, counts[1]: pixels they cover.
+// Recomputation list and work counters.  counts[0]: listed tiles, counts[1]: listed
+// pixels, counts[2]: next tile of a batched fitting pass, counts[3]: next listed tile of a
+// batched recomputation pass.  An entry is (frame << 24) | tile index in its frame.
+struct TileList {
+    uint32_t* entries;
+    uint64_t* masks;     // 4 words (256 pixel bits) per entry
+    uint32_t* counts;
+};
+
 __global__ void zero_counts(uint32_t* counts) {
-    counts[0] = 0u;
-    counts[1] = 0u;
+    if (threadIdx.x < 4) counts[threadIdx.x] = 0u;
 }
 
 // Stages the depth samples of a (w + 2 halo) x (h + 2 halo) region whose top-left pixel
-// is (x0, y0) into LDS as (D, pen) pairs.
+// is (x0, y0) into LDS as (D, c) pairs.
 __device__ __forceinline__ void stage_region(const FitDesc& d, float2* lds, int x0, int y0,
                                              int pitch, int rows) {
     for (int i = threadIdx.x; i < pitch * rows; i += blockDim.x) {
@@ -445,103 +497,240 @@ __device__ __forceinline__ PixelFit<Real> missing_pixel() {
     return r;
 }
 
-// Tiled pass: a kTileW x TH tile per workgroup, halo staged in LDS, one lane per pixel.
-// In FP32 (MIXED) every wave lists the lanes whose fit is judged unreliable: one entry
-// per 16x4 block of pixels with a 64-bit lane mask.
-template <typename Real, int R, int TH>
-__global__ __launch_bounds__(kTileW* TH) void fit_tile(FitDesc d, uint32_t* entries,
-                                                       uint64_t* masks, uint32_t* counts) {
+__device__ __forceinline__ int tiles_across(const FitDesc& d) {
+    return (d.width + d.tile_w - 1) / d.tile_w;
+}
+
+// One tile of tw x (blockDim.x / tw) pixels, halo staged in LDS, one lane per pixel.  In
+// FP32 (MIXED / FP32) a tile holding unreliable fits is listed once with a 256-bit mask of
+// those pixels (bit t = thread t = pixel (t % tw, t / tw)).
+template <typename Real, int R>
+__device__ __forceinline__ void fit_tile_body(const FitDesc& d, int tx, int ty, uint32_t frame,
+                                              const TileList& list) {
     extern __shared__ float2 tile[];
+    __shared__ uint64_t wave_masks[4];
+    const int tw = d.tile_w, th = blockDim.x / tw;
     const int halo = max(R, d.normal_radius);
-    const int pitch = kTileW + 2 * halo;
-    stage_region(d, tile, blockIdx.x * kTileW - halo, blockIdx.y * TH - halo, pitch, TH + 2 * halo);
-    const int lx = threadIdx.x % kTileW, ly = threadIdx.x / kTileW;
-    const int u = blockIdx.x * kTileW + lx, v = blockIdx.y * TH + ly;
-    const bool inside = u < d.width && v < d.height;
+    const int pitch = tw + 2 * halo;
+    stage_region(d, tile, tx * tw - halo, ty * th - halo, pitch, th + 2 * halo);
+    const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
+    const int u = tx * tw + lx, v = ty * th + ly;
     bool recompute = false;
-    if (inside) {
+    if (u < d.width && v < d.height) {
         const float2* centre = tile + (ly + halo) * pitch + (lx + halo);
-        const PixelFit<Real> r = centre->y != 0.f
+        const PixelFit<Real> r = !present(*centre)
             ? missing_pixel<Real>()
             : fit_pixel<Real, R>(d, LdsSource{centre, pitch}, u, v, centre->x, d.residual != nullptr);
         store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
         recompute = (r.flags & kFlagIll) != 0;
     }
-    if (sizeof(Real) == 4 && d.precision != 2) {
-        const uint64_t mask = __ballot(recompute);
-        if (mask != 0 && (threadIdx.x % 64) == 0) {
-            // 16x4 block index: (row of 4-pixel bands) * tiles_x + tile column
-            const uint32_t tiles_x = (d.width + kTileW - 1) / kTileW;
-            const uint32_t band = (blockIdx.y * TH + (threadIdx.x / 64) * 4) / 4;
-            const uint32_t slot = atomicAdd(&counts[0], 1u);
-            entries[slot] = band * tiles_x + blockIdx.x;
-            masks[slot] = mask;
-            atomicAdd(&counts[1], static_cast<uint32_t>(__popcll(mask)));
+    if constexpr (sizeof(Real) == 4) {
+        if (d.precision != 2) {
+            const uint64_t mask = __ballot(recompute);
+            if ((threadIdx.x % 64) == 0) wave_masks[threadIdx.x / 64] = mask;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint64_t m[4] = {0, 0, 0, 0};
+                for (int w = 0; w < static_cast<int>(blockDim.x / 64); ++w) m[w] = wave_masks[w];
+                if ((m[0] | m[1] | m[2] | m[3]) != 0) {
+                    const uint32_t slot = atomicAdd(&list.counts[0], 1u);
+                    list.entries[slot] = (frame << 24) | static_cast<uint32_t>(ty * tiles_across(d) + tx);
+                    for (int w = 0; w < 4; ++w) list.masks[4 * slot + w] = m[w];
+                    atomicAdd(&list.counts[1], static_cast<uint32_t>(__popcll(m[0]) + __popcll(m[1]) +
+                                                                     __popcll(m[2]) + __popcll(m[3])));
+                }
+            }
+            __syncthreads();   // wave_masks is reused by the next tile of a persistent loop
         }
     }
 }
 
-// FP64 recomputation of listed pixels: one 64-lane workgroup per 16x4 block entry,
-// halo staged in LDS, lanes whose mask bit is set run the fit.
+// Calls f(std::integral_constant<int, r>) for the window radius r in 1..kMaxRadius.
+template <typename F, int... Rs>
+__device__ __forceinline__ void with_radius(int r, F&& f, std::integer_sequence<int, Rs...>) {
+    (void)((r == Rs + 1 ? (f(std::integral_constant<int, Rs + 1>{}), true) : false) || ...);
+}
+template <typename F>
+__device__ __forceinline__ void with_radius(int r, F&& f) {
+    with_radius(r, f, std::make_integer_sequence<int, kMaxRadius>{});
+}
+
+// FP32 pass over one frame: one 256-lane workgroup per tile.
 template <int R>
-__global__ __launch_bounds__(64) void refit_blocks_f64(FitDesc d, const uint32_t* entries,
-                                                       const uint64_t* masks,
-                                                       const uint32_t* counts) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))
+void fit_tile_f32(FitDesc d, TileList list) {
+    fit_tile_body<float, R>(d, blockIdx.x, blockIdx.y, 0u, list);
+}
+
+// FP64 pass over every pixel of one frame: 16x4 tiles.
+template <int R>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+void fit_tile_f64(FitDesc d, TileList list) {
+    fit_tile_body<double, R>(d, blockIdx.x, blockIdx.y, 0u, list);
+}
+
+// Persistent FP32 pass over a batch of frames.  Tiles are numbered frame after frame
+// (frames ordered by the host from most to least work per tile; first_tile[f] is the
+// number of the frame's first tile, first_tile[n] the total); every workgroup takes the
+// next tile number from counts[2] until none is left, so all frames share one launch.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))
+void fit_batch_f32(const FitDesc* frames, const uint32_t* first_tile, const uint32_t* header,
+                   TileList list) {
+    __shared__ uint32_t next;
+    const uint32_t nf = header[0];
+    if (nf == 0) return;
+    const uint32_t total = first_tile[nf];
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(&list.counts[2], 1u);
+        __syncthreads();
+        const uint32_t t = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();
+        if (t >= total) break;
+        uint32_t lo = 0, hi = nf - 1;   // the frame holding tile t
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) / 2;
+            if (first_tile[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        const FitDesc d = frames[lo];
+        const int local = static_cast<int>(t - first_tile[lo]);
+        const int across = tiles_across(d);
+        with_radius(d.radius, [&](auto rc) {
+            fit_tile_body<float, decltype(rc)::value>(d, local % across, local / across, lo, list);
+        });
+        __syncthreads();   // the next tile re-stages LDS
+    }
+}
+
+// Position (0..63) of the n-th set bit (n counted from 0) of m; m has more than n bits.
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
+    int pos = 0;
+#pragma unroll
+    for (int width = 32; width >= 1; width >>= 1) {
+        const uint64_t low = m & ((uint64_t{1} << width) - 1);
+        const int c = __popcll(low);
+        if (n >= c) {
+            n -= c;
+            m >>= width;
+            pos += width;
+        } else {
+            m = low;
+        }
+    }
+    return pos;
+}
+
+// FP64 recomputation of the listed pixels of one listed tile by a 256-lane workgroup:
+// tile plus halo staged in LDS; each listed pixel is fitted by a group of kRefitLanes
+// lanes that split its window rows (the listed pixels are few, so one lane per pixel
+// would leave most SIMDs idle); the tile's listed pixels are taken 256/kRefitLanes at a
+// time in mask order.
+constexpr int kRefitLanes = 4;
+
+template <int R>
+__device__ __forceinline__ void refit_tile_body(const FitDesc& d, uint32_t tile_index,
+                                                const uint64_t* mask_words) {
     extern __shared__ float2 tile[];
-    const uint32_t n = counts[0];
-    const uint32_t tiles_x = (d.width + kTileW - 1) / kTileW;
+    const int tw = d.tile_w, th = 256 / tw;
+    const int across = tiles_across(d);
+    const int bx = static_cast<int>(tile_index % across) * tw;
+    const int by = static_cast<int>(tile_index / across) * th;
     const int halo = max(R, d.normal_radius);
-    const int pitch = kTileW + 2 * halo;
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const uint32_t e = entries[i];
-        const uint64_t mask = masks[i];
-        const int bx = static_cast<int>(e % tiles_x) * kTileW;
-        const int by = static_cast<int>(e / tiles_x) * 4;
-        stage_region(d, tile, bx - halo, by - halo, pitch, 4 + 2 * halo);
-        const int lx = threadIdx.x % kTileW, ly = threadIdx.x / kTileW;
-        if ((mask >> threadIdx.x) & 1u) {
+    const int pitch = tw + 2 * halo;
+    stage_region(d, tile, bx - halo, by - halo, pitch, th + 2 * halo);
+    const int group = threadIdx.x / kRefitLanes;
+    const LaneGroup<kRefitLanes> grp{static_cast<int>(threadIdx.x % kRefitLanes)};
+    uint64_t m[4];
+    int total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        m[w] = mask_words[w];
+        total += __popcll(m[w]);
+    }
+    for (int base = 0; base < total; base += 256 / kRefitLanes) {
+        const int t = base + group;   // rank of this group's pixel among the listed ones
+        if (t < total) {
+            int before = 0, word = 0, rank = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int c = __popcll(m[w]);
+                if (t >= before && t < before + c) {
+                    word = w;
+                    rank = t - before;
+                }
+                before += c;
+            }
+            const int thread = word * 64 + nth_set_bit(m[word], rank);
+            const int lx = thread % tw, ly = thread / tw;
             const int u = bx + lx, v = by + ly;
             const float2* centre = tile + (ly + halo) * pitch + (lx + halo);
-            const PixelFit<double> r =
-                fit_pixel<double, R>(d, LdsSource{centre, pitch}, u, v, centre->x, d.residual != nullptr);
-            store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
+            const PixelFit<double> r = fit_pixel<double, R, kRefitLanes>(
+                d, LdsSource{centre, pitch}, u, v, centre->x, d.residual != nullptr, grp);
+            if (grp.part == 0) store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
         }
-        __syncthreads();   // the next entry re-stages the LDS region
+    }
+    __syncthreads();   // the next entry re-stages the LDS region
+}
+
+// FP64 recomputation for one frame: workgroups stride over the listed tiles.
+template <int R>
+__global__ __launch_bounds__(256) void refit_tiles_f64(FitDesc d, TileList list) {
+    const uint32_t n = list.counts[0];
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
+        refit_tile_body<R>(d, list.entries[i] & 0xffffffu, list.masks + 4 * i);
+}
+
+// FP64 recomputation for a batch (header[1] != 0): workgroups take listed tiles from
+// counts[3].
+__global__ __launch_bounds__(256) void refit_batch_f64(const FitDesc* frames, const uint32_t* header,
+                                                       TileList list) {
+    __shared__ uint32_t next;
+    if (header[1] == 0) return;
+    const uint32_t n = list.counts[0];
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(&list.counts[3], 1u);
+        __syncthreads();
+        const uint32_t i = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();
+        if (i >= n) break;
+        const uint32_t e = __builtin_amdgcn_readfirstlane(list.entries[i]);
+        const FitDesc d = frames[e >> 24];
+        with_radius(d.radius, [&](auto rc) {
+            refit_tile_body<decltype(rc)::value>(d, e & 0xffffffu, list.masks + 4 * i);
+        });
     }
 }
 
+size_t lds_bytes(int tile_w, int tile_h, int halo) {
+    return sizeof(float2) * static_cast<size_t>(tile_w + 2 * halo) * static_cast<size_t>(tile_h + 2 * halo);
+}
+
 template <int R>
-hipError_t launch_radius(const FitDesc& d, uint32_t* entries, uint64_t* masks, uint32_t* counts,
-                         hipStream_t st, hipEvent_t* ev) {
+hipError_t launch_radius(const FitDesc& d, const TileList& list, hipStream_t st, hipEvent_t* ev) {
     const int halo = R > d.normal_radius ? R : d.normal_radius;
-    const uint32_t tiles_x = (d.width + kTileW - 1) / kTileW;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if (d.precision == 2) {
-        constexpr int TH = 4;
-        const size_t lds = sizeof(float2) * (kTileW + 2 * halo) * (TH + 2 * halo);
-        dim3 grid(tiles_x, (d.height + TH - 1) / TH);
-        hipLaunchKernelGGL((fit_tile<double, R, TH>), grid, dim3(kTileW * TH), lds, st, d, entries,
-                           masks, counts);
+        FitDesc d64 = d;
+        d64.tile_w = kTileW;
+        dim3 grid((d.width + kTileW - 1) / kTileW, (d.height + 3) / 4);
+        hipLaunchKernelGGL(fit_tile_f64<R>, grid, dim3(64), lds_bytes(kTileW, 4, halo), st, d64, list);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
         return hipSuccess;
     }
-    constexpr int TH = 16;
-    const size_t lds = sizeof(float2) * (kTileW + 2 * halo) * (TH + 2 * halo);
-    dim3 grid(tiles_x, (d.height + TH - 1) / TH);
-    hipLaunchKernelGGL((fit_tile<float, R, TH>), grid, dim3(kTileW * TH), lds, st, d, entries, masks,
-                       counts);
+    const int tw = d.tile_w, th = 256 / tw;
+    const size_t lds = lds_bytes(tw, th, halo);
+    dim3 grid((d.width + tw - 1) / tw, (d.height + th - 1) / th);
+    hipLaunchKernelGGL(fit_tile_f32<R>, grid, dim3(256), lds, st, d, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
     if (d.precision == 0) {
-        // One workgroup per listed block in the worst case, capped; each loops over entries.
-        const uint32_t blocks = tiles_x * grid.y * (TH / 4);
-        const uint32_t nwg = blocks < 8192u ? blocks : 8192u;
-        const size_t lds64 = sizeof(float2) * (kTileW + 2 * halo) * (4 + 2 * halo);
-        hipLaunchKernelGGL(refit_blocks_f64<R>, dim3(nwg), dim3(64), lds64, st, d, entries, masks,
-                           counts);
+        // one workgroup per listed tile in the worst case, capped; each loops over entries
+        const uint32_t tiles = grid.x * grid.y;
+        const uint32_t nwg = tiles < 4096u ? tiles : 4096u;
+        hipLaunchKernelGGL(refit_tiles_f64<R>, dim3(nwg), dim3(256), lds, st, d, list);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
@@ -549,31 +738,65 @@ hipError_t launch_radius(const FitDesc& d, uint32_t* entries, uint64_t* masks, u
 }
 
 template <int... Rs>
-hipError_t dispatch_radius(int r, const FitDesc& d, uint32_t* entries, uint64_t* masks,
-                           uint32_t* counts, hipStream_t st, hipEvent_t* ev,
-                           std::integer_sequence<int, Rs...>) {
+hipError_t dispatch_radius(int r, const FitDesc& d, const TileList& list, hipStream_t st,
+                           hipEvent_t* ev, std::integer_sequence<int, Rs...>) {
     hipError_t e = hipErrorInvalidValue;
-    (void)((r == Rs + 1 ? (e = launch_radius<Rs + 1>(d, entries, masks, counts, st, ev), true) : false) || ...);
+    (void)((r == Rs + 1 ? (e = launch_radius<Rs + 1>(d, list, st, ev), true) : false) || ...);
     return e;
 }
 
 }  // namespace
 
-int64_t refit_capacity(int width, int height) {
-    const int64_t tiles_x = (width + kTileW - 1) / kTileW;
-    const int64_t tiles_y = (height + 15) / 16;
-    return tiles_x * tiles_y * 4;
+int64_t refit_capacity(int width, int height, int tile_w) {
+    const int64_t th = 256 / tile_w;
+    return ((width + tile_w - 1) / tile_w) * static_cast<int64_t>((height + th - 1) / th);
+}
+
+bool valid_tile_width(int tile_w) {
+    return tile_w == 8 || tile_w == 16 || tile_w == 32 || tile_w == 64;
 }
 
 hipError_t launch_fit(const FitDesc& d, uint32_t* entries, uint64_t* masks, uint32_t* counts,
                       hipStream_t stream, hipEvent_t* events) {
+    const TileList list{entries, masks, counts};
     if (d.precision != 2) {
-        hipLaunchKernelGGL(zero_counts, dim3(1), dim3(1), 0, stream, counts);
+        hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, counts);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return dispatch_radius(d.radius, d, entries, masks, counts, stream, events,
+    return dispatch_radius(d.radius, d, list, stream, events,
                            std::make_integer_sequence<int, kMaxRadius>{});
+}
+
+size_t batch_lds_bytes() {
+    // largest staging region over the supported tile shapes at the largest halo
+    size_t m = 0;
+    for (int tw = 8; tw <= 64; tw *= 2) {
+        const size_t b = lds_bytes(tw, 256 / tw, kMaxRadius);
+        m = b > m ? b : m;
+    }
+    return m;
+}
+
+hipError_t launch_fit_batch(const FitDesc* frames, const uint32_t* first_tile,
+                            const uint32_t* header, int workgroups, uint32_t* entries,
+                            uint64_t* masks, uint32_t* counts, hipStream_t stream,
+                            hipEvent_t* events) {
+    const TileList list{entries, masks, counts};
+    hipError_t e;
+    hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, counts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t lds = batch_lds_bytes();
+    if (events && (e = hipEventRecord(events[0], stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(fit_batch_f32, dim3(workgroups), dim3(256), lds, stream, frames, first_tile,
+                       header, list);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (events && (e = hipEventRecord(events[1], stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(refit_batch_f64, dim3(workgroups), dim3(256), lds, stream, frames, header,
+                       list);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (events && (e = hipEventRecord(events[2], stream)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 }  // namespace qc

@@ -1,22 +1,57 @@
 // qcurv_api.cpp -- the C ABI of libqcurv.so (declared in include/qcurv.h): argument
-// validation, per-context scratch and the hand-off to the HIP kernels.
+// validation, per-context scratch, batch graphs, tuning table and the hand-off to the
+// HIP kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <tuple>
 #include <vector>
 
+#include "api_internal.h"
 #include "fit_internal.h"
 #include "qcurv.h"
 
+namespace {
+
+// Host staging of one batch: descriptors, tile prefix sums and a two-word header, copied
+// to the device by the first node of the batch graph.
+struct BatchStaging {
+    qc::FitDesc frames[QC_MAX_BATCH];
+    uint32_t first_tile[QC_MAX_BATCH + 1];
+    uint32_t header[2];   // [0] frames, [1] recompute listed pixels in FP64
+};
+
+// One of the two batches a context may have in flight.
+struct BatchSlot {
+    BatchStaging* host = nullptr;   // pinned
+    BatchStaging* dev = nullptr;
+    uint32_t* entries = nullptr;
+    uint64_t* masks = nullptr;
+    uint32_t* counts = nullptr;
+    int64_t capacity = 0;           // tile entries
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;      // recorded after the slot's last use
+    bool in_flight = false;
+};
+
+using TuneKey = std::tuple<int, int, int, int>;   // width, height, radius, iterations
+
+}  // namespace
+
 struct qc_context {
     int device = 0;
+    int cus = 0;
     int last_hip_error = 0;
-    uint32_t* refit_entries = nullptr; // device, capacity 16x4-block indices
-    uint64_t* refit_masks = nullptr;   // device, capacity lane masks
-    uint32_t* refit_counts = nullptr;  // device, [entries, pixels]
+    uint32_t* refit_entries = nullptr; // device, capacity tile indices
+    uint64_t* refit_masks = nullptr;   // device, 4 x capacity words (256-bit pixel masks)
+    uint32_t* refit_counts = nullptr;  // device, 4 counters
     int64_t capacity = 0;
     hipStream_t last_stream = nullptr;
     int last_precision = 0;
@@ -24,6 +59,12 @@ struct qc_context {
     bool timing = false;
     std::vector<hipEvent_t> pending;
     qc_timing sums{};
+    // batches
+    BatchSlot slots[2];
+    int next_slot = 0;
+    hipStream_t capture_stream = nullptr;
+    // tuned FP32 tile widths
+    std::map<TuneKey, int> tuned;
 };
 
 namespace {
@@ -51,6 +92,7 @@ qc_status check_params(const qc_params* p) {
     if (!(p->depth_scale > 0.f) || !std::isfinite(p->depth_scale)) return QC_ERR_INVALID_ARG;
     if (p->precision < QC_PREC_MIXED || p->precision > QC_PREC_FP64) return QC_ERR_INVALID_ARG;
     if (std::isnan(p->cond_max) || std::isnan(p->step_max)) return QC_ERR_INVALID_ARG;
+    if (p->tile_width != 0 && !qc::valid_tile_width(p->tile_width)) return QC_ERR_INVALID_ARG;
     if (p->reject != 0) return QC_ERR_UNSUPPORTED;
     return QC_OK;
 }
@@ -60,8 +102,9 @@ qc_status check_frame(const qc_frame* f) {
     const int sb = sample_bytes(f->format);
     if (sb == 0) return QC_ERR_INVALID_ARG;
     if (f->width < 1 || f->height < 1) return QC_ERR_INVALID_ARG;
-    // pixel indices are kept in 32 bits
+    // pixel indices are kept in 32 bits, tile indices in 24
     if (static_cast<int64_t>(f->width) * f->height > (int64_t{1} << 31)) return QC_ERR_INVALID_ARG;
+    if (qc::refit_capacity(f->width, f->height, 8) >= (int64_t{1} << 24)) return QC_ERR_INVALID_ARG;
     if (f->pitch_bytes < static_cast<int64_t>(f->width) * sb || f->pitch_bytes % sb != 0)
         return QC_ERR_INVALID_ARG;
     const qc_intrinsics& K = f->K;
@@ -71,98 +114,20 @@ qc_status check_frame(const qc_frame* f) {
     return QC_OK;
 }
 
-qc_status ensure_capacity(qc_context* ctx, int64_t entries) {
-    if (ctx->capacity >= entries) return QC_OK;
-    hipError_t e;
-    if (ctx->refit_entries) {
-        // the previous lists may still be in use by enqueued work
-        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(ctx, e);
-        (void)hipFree(ctx->refit_entries);
-        (void)hipFree(ctx->refit_masks);
-        ctx->refit_entries = nullptr;
-        ctx->refit_masks = nullptr;
-        ctx->capacity = 0;
-    }
-    void* p = nullptr;
-    void* q = nullptr;
-    if ((e = hipMalloc(&p, sizeof(uint32_t) * static_cast<size_t>(entries))) != hipSuccess)
-        return hip_fail(ctx, e);
-    if ((e = hipMalloc(&q, sizeof(uint64_t) * static_cast<size_t>(entries))) != hipSuccess) {
-        (void)hipFree(p);
-        return hip_fail(ctx, e);
-    }
-    ctx->refit_entries = static_cast<uint32_t*>(p);
-    ctx->refit_masks = static_cast<uint64_t*>(q);
-    ctx->capacity = entries;
-    return QC_OK;
+int64_t max_tiles(int width, int height) {
+    int64_t m = 0;
+    for (int tw = 8; tw <= 64; tw *= 2) m = std::max(m, qc::refit_capacity(width, height, tw));
+    return m;
 }
 
-}  // namespace
-
-extern "C" {
-
-void qc_params_default(qc_params* p) {
-    if (!p) return;
-    p->radius = 7;
-    p->normal_radius = 3;
-    p->iterations = 5;
-    p->k = 1e-5f;
-    p->reject = 0;
-    p->depth_scale = 1e-3f;
-    p->precision = QC_PREC_MIXED;
-    p->cond_max = 30.f;
-    p->step_max = 1e-1f;
+int tile_width_for(const qc_context* ctx, const qc_frame* f, const qc_params* p) {
+    if (p->tile_width != 0) return p->tile_width;
+    auto it = ctx->tuned.find(TuneKey{f->width, f->height, p->radius, p->iterations});
+    return it != ctx->tuned.end() ? it->second : 16;
 }
 
-qc_status qc_create(qc_context** out, int device) {
-    if (!out) return QC_ERR_INVALID_ARG;
-    *out = nullptr;
-    int n = 0;
-    hipError_t e = hipGetDeviceCount(&n);
-    if (e != hipSuccess) return QC_ERR_HIP;
-    if (device < 0 || device >= n) return QC_ERR_INVALID_ARG;
-    qc_context* ctx = new (std::nothrow) qc_context();
-    if (!ctx) return QC_ERR_OOM;
-    ctx->device = device;
-    if ((e = hipSetDevice(device)) != hipSuccess) {
-        delete ctx;
-        return QC_ERR_HIP;
-    }
-    void* p = nullptr;
-    if ((e = hipMalloc(&p, 2 * sizeof(uint32_t))) != hipSuccess) {
-        delete ctx;
-        return e == hipErrorOutOfMemory ? QC_ERR_OOM : QC_ERR_HIP;
-    }
-    ctx->refit_counts = static_cast<uint32_t*>(p);
-    *out = ctx;
-    return QC_OK;
-}
-
-qc_status qc_destroy(qc_context* ctx) {
-    if (!ctx) return QC_OK;
-    (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();
-    if (ctx->refit_entries) (void)hipFree(ctx->refit_entries);
-    if (ctx->refit_masks) (void)hipFree(ctx->refit_masks);
-    if (ctx->refit_counts) (void)hipFree(ctx->refit_counts);
-    for (hipEvent_t ev : ctx->pending) (void)hipEventDestroy(ev);
-    delete ctx;
-    return QC_OK;
-}
-
-qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params,
-                 const qc_output* out, void* stream) {
-    if (!ctx) return QC_ERR_INVALID_ARG;
-    qc_status st;
-    if ((st = check_frame(frame)) != QC_OK) return st;
-    if ((st = check_params(params)) != QC_OK) return st;
-    if (!out || !out->k1 || !out->k2) return QC_ERR_INVALID_ARG;
-    hipError_t e;
-    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
-    const int64_t entries = qc::refit_capacity(frame->width, frame->height);
-    if (params->precision != QC_PREC_FP64 && (st = ensure_capacity(ctx, entries)) != QC_OK)
-        return st;
-
+qc::FitDesc make_desc(const qc_frame* frame, const qc_params* params, const qc_output* out,
+                      int tile_w) {
     qc::FitDesc d;
     d.depth = frame->depth;
     d.format = frame->format;
@@ -181,11 +146,191 @@ qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params
     d.cond_max = params->cond_max;
     d.step_max = params->step_max;
     d.precision = params->precision;
+    d.tile_w = tile_w;
     d.k1 = out->k1;
     d.k2 = out->k2;
     d.normal = out->normal;
     d.residual = out->residual;
     d.flags = out->flags;
+    return d;
+}
+
+qc_status ensure_capacity(qc_context* ctx, int64_t entries) {
+    if (ctx->capacity >= entries) return QC_OK;
+    hipError_t e;
+    if (ctx->refit_entries) {
+        // the previous lists may still be in use by enqueued work
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(ctx, e);
+        (void)hipFree(ctx->refit_entries);
+        (void)hipFree(ctx->refit_masks);
+        ctx->refit_entries = nullptr;
+        ctx->refit_masks = nullptr;
+        ctx->capacity = 0;
+    }
+    void* p = nullptr;
+    void* q = nullptr;
+    if ((e = hipMalloc(&p, sizeof(uint32_t) * static_cast<size_t>(entries))) != hipSuccess)
+        return hip_fail(ctx, e);
+    if ((e = hipMalloc(&q, 4 * sizeof(uint64_t) * static_cast<size_t>(entries))) != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail(ctx, e);
+    }
+    ctx->refit_entries = static_cast<uint32_t*>(p);
+    ctx->refit_masks = static_cast<uint64_t*>(q);
+    ctx->capacity = entries;
+    return QC_OK;
+}
+
+void free_slot(BatchSlot& s) {
+    if (s.exec) (void)hipGraphExecDestroy(s.exec);
+    if (s.graph) (void)hipGraphDestroy(s.graph);
+    if (s.entries) (void)hipFree(s.entries);
+    if (s.masks) (void)hipFree(s.masks);
+    s.exec = nullptr;
+    s.graph = nullptr;
+    s.entries = nullptr;
+    s.masks = nullptr;
+    s.capacity = 0;
+}
+
+// Makes `s` hold scratch for `entries` tiles and a graph bound to it.  The graph is the
+// staging upload, a counter-reset kernel and the two persistent passes; it holds no
+// memset node.
+qc_status prepare_slot(qc_context* ctx, BatchSlot& s, int64_t entries) {
+    hipError_t e;
+    if (!s.host) {
+        void* h = nullptr;
+        void* dv = nullptr;
+        void* c = nullptr;
+        if ((e = hipHostMalloc(&h, sizeof(BatchStaging), hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(ctx, e);
+        s.host = static_cast<BatchStaging*>(h);
+        if ((e = hipMalloc(&dv, sizeof(BatchStaging))) != hipSuccess) return hip_fail(ctx, e);
+        s.dev = static_cast<BatchStaging*>(dv);
+        if ((e = hipMalloc(&c, 4 * sizeof(uint32_t))) != hipSuccess) return hip_fail(ctx, e);
+        s.counts = static_cast<uint32_t*>(c);
+        if ((e = hipEventCreate(&s.done)) != hipSuccess) return hip_fail(ctx, e);
+    }
+    if (s.capacity >= entries && s.exec) return QC_OK;
+    free_slot(s);
+    const int64_t cap = std::max<int64_t>(entries, 1 << 16);
+    void* p = nullptr;
+    void* q = nullptr;
+    if ((e = hipMalloc(&p, sizeof(uint32_t) * static_cast<size_t>(cap))) != hipSuccess)
+        return hip_fail(ctx, e);
+    s.entries = static_cast<uint32_t*>(p);
+    if ((e = hipMalloc(&q, 4 * sizeof(uint64_t) * static_cast<size_t>(cap))) != hipSuccess)
+        return hip_fail(ctx, e);
+    s.masks = static_cast<uint64_t*>(q);
+    s.capacity = cap;
+    hipStream_t cs = ctx->capture_stream;
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(ctx, e);
+    hipError_t le = hipMemcpyAsync(s.dev, s.host, sizeof(BatchStaging), hipMemcpyHostToDevice, cs);
+    if (le == hipSuccess)
+        le = qc::launch_fit_batch(s.dev->frames, s.dev->first_tile, s.dev->header, 4 * ctx->cus,
+                                  s.entries, s.masks, s.counts, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(ctx, le);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e);
+    s.graph = g;
+    if ((e = hipGraphInstantiate(&s.exec, g, nullptr, nullptr, 0)) != hipSuccess)
+        return hip_fail(ctx, e);
+    return QC_OK;
+}
+
+}  // namespace
+
+namespace qc {
+
+int context_device(const qc_context* ctx) { return ctx->device; }
+
+qc_status check_request(const qc_frame* frame, const qc_params* params) {
+    qc_status st = check_frame(frame);
+    return st != QC_OK ? st : check_params(params);
+}
+
+}  // namespace qc
+
+extern "C" {
+
+void qc_params_default(qc_params* p) {
+    if (!p) return;
+    p->radius = 7;
+    p->normal_radius = 3;
+    p->iterations = 5;
+    p->k = 1e-5f;
+    p->reject = 0;
+    p->depth_scale = 1e-3f;
+    p->precision = QC_PREC_MIXED;
+    p->cond_max = 30.f;
+    p->step_max = 1e-1f;
+    p->tile_width = 0;
+}
+
+qc_status qc_create(qc_context** out, int device) {
+    if (!out) return QC_ERR_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return QC_ERR_HIP;
+    if (device < 0 || device >= n) return QC_ERR_INVALID_ARG;
+    qc_context* ctx = new (std::nothrow) qc_context();
+    if (!ctx) return QC_ERR_OOM;
+    ctx->device = device;
+    int cus = 0;
+    void* p = nullptr;
+    if ((e = hipSetDevice(device)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess ||
+        (e = hipMalloc(&p, 4 * sizeof(uint32_t))) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
+        if (p) (void)hipFree(p);
+        delete ctx;
+        return e == hipErrorOutOfMemory ? QC_ERR_OOM : QC_ERR_HIP;
+    }
+    ctx->cus = cus > 0 ? cus : 1;
+    ctx->refit_counts = static_cast<uint32_t*>(p);
+    *out = ctx;
+    return QC_OK;
+}
+
+qc_status qc_destroy(qc_context* ctx) {
+    if (!ctx) return QC_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->refit_entries) (void)hipFree(ctx->refit_entries);
+    if (ctx->refit_masks) (void)hipFree(ctx->refit_masks);
+    if (ctx->refit_counts) (void)hipFree(ctx->refit_counts);
+    for (hipEvent_t ev : ctx->pending) (void)hipEventDestroy(ev);
+    for (BatchSlot& s : ctx->slots) {
+        free_slot(s);
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.counts) (void)hipFree(s.counts);
+        if (s.done) (void)hipEventDestroy(s.done);
+    }
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    delete ctx;
+    return QC_OK;
+}
+
+qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params,
+                 const qc_output* out, void* stream) {
+    if (!ctx) return QC_ERR_INVALID_ARG;
+    qc_status st;
+    if ((st = check_frame(frame)) != QC_OK) return st;
+    if ((st = check_params(params)) != QC_OK) return st;
+    if (!out || !out->k1 || !out->k2) return QC_ERR_INVALID_ARG;
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
+    if (params->precision != QC_PREC_FP64 &&
+        (st = ensure_capacity(ctx, max_tiles(frame->width, frame->height))) != QC_OK)
+        return st;
+    const qc::FitDesc d = make_desc(frame, params, out, tile_width_for(ctx, frame, params));
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (ctx->timing) {
@@ -199,6 +344,143 @@ qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params
     ctx->last_stream = s;
     ctx->last_precision = params->precision;
     return QC_OK;
+}
+
+qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, void* stream) {
+    if (!ctx || n < 0 || n > QC_MAX_BATCH || (n > 0 && !items)) return QC_ERR_INVALID_ARG;
+    if (n == 0) return QC_OK;
+    qc_status st;
+    const int32_t prec = items[0].params.precision;
+    for (int32_t i = 0; i < n; ++i) {
+        const qc_batch_item& it = items[i];
+        if ((st = check_frame(&it.frame)) != QC_OK) return st;
+        if ((st = check_params(&it.params)) != QC_OK) return st;
+        if (!it.out.k1 || !it.out.k2) return QC_ERR_INVALID_ARG;
+        if (it.params.precision != prec) return QC_ERR_INVALID_ARG;
+    }
+    if (prec == QC_PREC_FP64) return QC_ERR_UNSUPPORTED;
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
+
+    // frames from most to least work per tile, so the long tiles start first
+    std::vector<int32_t> order(n);
+    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    auto cost = [&](int32_t i) {
+        const int r = items[i].params.radius;
+        return static_cast<int64_t>(2 * r + 1) * (2 * r + 1) * std::max(1, items[i].params.iterations);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+    std::vector<qc::FitDesc> descs(n);
+    std::vector<uint32_t> first(n + 1, 0);
+    for (int32_t j = 0; j < n; ++j) {
+        const qc_batch_item& it = items[order[j]];
+        const int tw = tile_width_for(ctx, &it.frame, &it.params);
+        descs[j] = make_desc(&it.frame, &it.params, &it.out, tw);
+        first[j + 1] = first[j] + static_cast<uint32_t>(qc::refit_capacity(it.frame.width, it.frame.height, tw));
+    }
+    if (first[n] >= (1u << 24)) return QC_ERR_INVALID_ARG;
+
+    BatchSlot& s = ctx->slots[ctx->next_slot];
+    if (s.in_flight) {
+        // the slot's staging and lists may still be read by its previous batch
+        if ((e = hipEventSynchronize(s.done)) != hipSuccess) return hip_fail(ctx, e);
+        s.in_flight = false;
+    }
+    if ((st = prepare_slot(ctx, s, first[n])) != QC_OK) return st;
+    std::memcpy(s.host->frames, descs.data(), sizeof(qc::FitDesc) * n);
+    std::memcpy(s.host->first_tile, first.data(), sizeof(uint32_t) * (n + 1));
+    s.host->header[0] = static_cast<uint32_t>(n);
+    s.host->header[1] = prec == QC_PREC_MIXED ? 1u : 0u;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (ctx->timing) {
+        // timed batches run eagerly so that the two passes can be bracketed separately
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        for (auto& x : ev)
+            if ((e = hipEventCreate(&x)) != hipSuccess) return hip_fail(ctx, e);
+        ctx->pending.insert(ctx->pending.end(), ev, ev + 3);
+        if ((e = hipMemcpyAsync(s.dev, s.host, sizeof(BatchStaging), hipMemcpyHostToDevice, hs)) != hipSuccess ||
+            (e = qc::launch_fit_batch(s.dev->frames, s.dev->first_tile, s.dev->header, 4 * ctx->cus,
+                                      s.entries, s.masks, s.counts, hs, ev)) != hipSuccess)
+            return hip_fail(ctx, e);
+    } else if ((e = hipGraphLaunch(s.exec, hs)) != hipSuccess) {
+        return hip_fail(ctx, e);
+    }
+    if ((e = hipEventRecord(s.done, hs)) != hipSuccess) return hip_fail(ctx, e);
+    s.in_flight = true;
+    ctx->next_slot ^= 1;
+    return QC_OK;
+}
+
+qc_status qc_tune(qc_context* ctx, const qc_frame* frame, const qc_params* params,
+                  const qc_output* out, int32_t reps, void* stream, int32_t* tile_width) {
+    if (!ctx || reps < 1) return QC_ERR_INVALID_ARG;
+    qc_status st;
+    if ((st = check_frame(frame)) != QC_OK) return st;
+    if ((st = check_params(params)) != QC_OK) return st;
+    if (!out || !out->k1 || !out->k2) return QC_ERR_INVALID_ARG;
+    hipError_t e;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t a = nullptr, b = nullptr;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess || (e = hipEventCreate(&a)) != hipSuccess ||
+        (e = hipEventCreate(&b)) != hipSuccess)
+        return hip_fail(ctx, e);
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    int best = 16;
+    float best_ms = 0.f;
+    for (int tw = 8; tw <= 64 && st == QC_OK; tw *= 2) {
+        qc_params p = *params;
+        p.tile_width = tw;
+        st = qc_fit(ctx, frame, &p, out, stream);   // warm-up
+        if (st == QC_OK && (e = hipEventRecord(a, s)) != hipSuccess) st = hip_fail(ctx, e);
+        for (int32_t i = 0; i < reps && st == QC_OK; ++i) st = qc_fit(ctx, frame, &p, out, stream);
+        float ms = 0.f;
+        if (st == QC_OK && ((e = hipEventRecord(b, s)) != hipSuccess ||
+                            (e = hipEventSynchronize(b)) != hipSuccess ||
+                            (e = hipEventElapsedTime(&ms, a, b)) != hipSuccess))
+            st = hip_fail(ctx, e);
+        if (st == QC_OK && (tw == 8 || ms < best_ms)) {
+            best = tw;
+            best_ms = ms;
+        }
+    }
+    ctx->timing = timing;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != QC_OK) return st;
+    ctx->tuned[TuneKey{frame->width, frame->height, params->radius, params->iterations}] = best;
+    if (tile_width) *tile_width = best;
+    return QC_OK;
+}
+
+qc_status qc_tune_save(qc_context* ctx, const char* path) {
+    if (!ctx || !path) return QC_ERR_INVALID_ARG;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return QC_ERR_INVALID_ARG;
+    for (const auto& kv : ctx->tuned)
+        std::fprintf(f, "%d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                     std::get<2>(kv.first), std::get<3>(kv.first), kv.second);
+    return std::fclose(f) == 0 ? QC_OK : QC_ERR_INVALID_ARG;
+}
+
+qc_status qc_tune_load(qc_context* ctx, const char* path) {
+    if (!ctx || !path) return QC_ERR_INVALID_ARG;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return QC_ERR_INVALID_ARG;
+    int w, h, r, t, tw;
+    qc_status st = QC_OK;
+    while (true) {
+        const int got = std::fscanf(f, "%d %d %d %d %d", &w, &h, &r, &t, &tw);
+        if (got == EOF) break;
+        if (got != 5 || w < 1 || h < 1 || r < 1 || r > QC_MAX_RADIUS || t < 0 ||
+            !qc::valid_tile_width(tw)) {
+            st = QC_ERR_INVALID_ARG;
+            break;
+        }
+        ctx->tuned[TuneKey{w, h, r, t}] = tw;
+    }
+    std::fclose(f);
+    return st;
 }
 
 qc_status qc_last_refit_count(qc_context* ctx, uint32_t* count) {

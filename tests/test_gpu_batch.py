@@ -1,0 +1,158 @@
+"""GPU tests of the batched form (one persistent launch over many frames, replayed from a
+captured HIP graph) and of tile-shape tuning: every frame's outputs must equal, bit for
+bit, those of the plain per-frame call, and the plain call must not depend on the tile
+shape.  The per-frame call is itself checked against the oracle in test_gpu_parity.py;
+one batch is also compared with the oracle directly here."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_1707_00385_amd import scenes
+from tests.helpers import compare, log, oracle_pair
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("k1", "k2", "normal", "residual", "flags")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1707_00385_amd.api import Context
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _jobs():
+    """Uneven frames: sizes, formats, radii 1..18, iterations 0..5, tile widths."""
+    specs = [
+        (scenes.Camera(96, 72, 80.0, 80.0, 47.5, 35.5), "u16", 3, 3, 8),
+        (scenes.Camera(100, 75, 90.0, 90.0, 49.5, 37.0), "f32", 5, 5, 16),
+        (scenes.Camera(64, 48, 60.0, 60.0, 31.5, 23.5), "f16", 7, 5, 32),
+        (scenes.Camera(160, 120, 131.25, 131.25, 80.0, 60.0), "u16", 11, 3, 64),
+        (scenes.Camera(33, 31, 40.0, 40.0, 16.0, 15.0), "f32", 18, 2, 16),
+        (scenes.Camera(17, 16, 40.0, 40.0, 8.0, 7.5), "u16", 1, 4, 0),
+        (scenes.Camera(40, 30, 40.0, 40.0, 19.5, 14.5), "f32", 4, 0, 0),
+    ]
+    out = []
+    for i, (cam, fmt, r, T, tw) in enumerate(specs):
+        sc = scenes.cluttered_scene(cam, seed_frame=40 + i, config_index=3)
+        depth = sc.depth_u16() if fmt == "u16" else sc.depth_m
+        out.append((sc, cam, fmt, depth, r, T, tw))
+    return out
+
+
+def _run_single(ctx, depth_t, cam, params):
+    import torch
+    from paper_1707_00385_amd.api import make_outputs
+    o = make_outputs(depth_t.shape[0], depth_t.shape[1], depth_t.device, normal=True, residual=True)
+    ctx.fit(depth_t, (cam.fx, cam.fy, cam.cx, cam.cy), params=params, out=o)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in o.items()}
+
+
+def _batch_jobs(jobs):
+    from paper_1707_00385_amd.api import make_outputs, make_params, upload_depth
+    bj, singles = [], []
+    for sc, cam, fmt, depth, r, T, tw in jobs:
+        t = upload_depth(depth, fmt)
+        p = make_params(radius=r, iterations=T, tile_width=tw)
+        o = make_outputs(t.shape[0], t.shape[1], t.device, normal=True, residual=True)
+        bj.append((t, (cam.fx, cam.fy, cam.cx, cam.cy), p, o))
+    return bj
+
+
+def _equal(a, b, what):
+    for k in KEYS:
+        assert np.array_equal(a[k], b[k], equal_nan=True), f"{what}: {k} differs"
+
+
+def test_tile_shape_does_not_change_results(ctx):
+    from paper_1707_00385_amd.api import make_params, upload_depth
+    sc = scenes.cluttered_scene(scenes.Camera(100, 75, 90.0, 90.0, 49.5, 37.0), seed_frame=3,
+                                config_index=8)
+    t = upload_depth(sc.depth_u16(), "u16")
+    ref = None
+    for tw in (8, 16, 32, 64):
+        log(f"[case] tile width {tw}")
+        r = _run_single(ctx, t, sc.camera, make_params(radius=5, iterations=5, tile_width=tw))
+        if ref is None:
+            ref = r
+        else:
+            _equal(r, ref, f"tile width {tw}")
+
+
+def test_batch_equals_per_frame_calls(ctx):
+    import torch
+    jobs = _jobs()
+    bj = _batch_jobs(jobs)
+    log(f"[case] batch of {len(bj)} uneven frames")
+    outs = ctx.fit_batch(bj)
+    torch.cuda.synchronize()
+    for i, ((t, K, p, _), o) in enumerate(zip(bj, outs)):
+        single = _run_single(ctx, t, jobs[i][1], p)
+        _equal({k: v.cpu().numpy() for k, v in o.items()}, single, f"frame {i}")
+
+
+def test_batch_graph_replays_match_eager(ctx):
+    """The batch runs from a captured graph; replay it several times with the program's
+    own GPU work and synchronisations in between, and check every replay."""
+    import torch
+    jobs = _jobs()[:4]
+    bj = _batch_jobs(jobs)
+    ref = [_run_single(ctx, t, jobs[i][1], p) for i, (t, K, p, _) in enumerate(bj)]
+    for rep in range(4):
+        log(f"[case] replay {rep}")
+        for _, _, _, o in bj:
+            for v in o.values():
+                v.fill_(0)
+        outs = ctx.fit_batch(bj)
+        x = torch.randn(1024, device="cuda:0").sum()   # unrelated eager work
+        torch.cuda.synchronize()
+        assert torch.isfinite(x)
+        for i, o in enumerate(outs):
+            _equal({k: v.cpu().numpy() for k, v in o.items()}, ref[i], f"replay {rep} frame {i}")
+
+
+def test_two_batches_in_flight_on_two_streams(ctx):
+    import torch
+    jobs = _jobs()
+    a, b = _batch_jobs(jobs[:3]), _batch_jobs(jobs[3:])
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    oa = ctx.fit_batch(a, stream=s1)
+    ob = ctx.fit_batch(b, stream=s2)
+    torch.cuda.synchronize()
+    for (t, K, p, _), o, j in zip(a + b, oa + ob, jobs):
+        _equal({k: v.cpu().numpy() for k, v in o.items()}, _run_single(ctx, t, j[1], p), "2 streams")
+
+
+def test_batch_against_oracle(ctx):
+    import torch
+    jobs = _jobs()[:3]
+    bj = _batch_jobs(jobs)
+    outs = ctx.fit_batch(bj)
+    torch.cuda.synchronize()
+    for (sc, cam, fmt, depth, r, T, tw), o in zip(jobs, outs):
+        g = {k: v.cpu().numpy() for k, v in o.items()}
+        ref, alt = oracle_pair(depth, fmt, cam, r, T, 1e-5)
+        compare(g, ref, 1e-3, f"batch {cam.width}x{cam.height} r={r}", o_alt=alt)
+
+
+def test_tune_records_and_round_trips(ctx):
+    from paper_1707_00385_amd.api import make_params, upload_depth
+    sc = scenes.cluttered_scene(scenes.Camera(128, 96, 100.0, 100.0, 63.5, 47.5), seed_frame=9,
+                                config_index=8)
+    t = upload_depth(sc.depth_u16(), "u16")
+    K = (sc.camera.fx, sc.camera.fy, sc.camera.cx, sc.camera.cy)
+    tw = ctx.tune(t, K, make_params(radius=3, iterations=3), reps=2)
+    assert tw in (8, 16, 32, 64)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        ctx.tune_save(path)
+        line = open(path).read().split()
+        assert line == ["128", "96", "3", "3", str(tw)]
+        ctx.tune_load(path)
