@@ -9,7 +9,9 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libqcurv.so")
+# QCURV_LIB may name another build of the same library (e.g. a variant compiled with
+# different occupancy settings); by default the in-tree build is used.
+LIB_PATH = os.environ.get("QCURV_LIB") or os.path.join(PKG, "libqcurv.so")
 
 QC_OK = 0
 QC_DEPTH_U16, QC_DEPTH_F16, QC_DEPTH_F32 = 0, 1, 2
