@@ -26,30 +26,45 @@ struct FitDesc {
     uint8_t* flags;
 };
 
-// Enqueues the whole fit of one frame on `stream`.  MIXED / FP32: a tiled FP32 pass that
-// lists the tiles holding unreliable fits (`entries`: refit_capacity() tile indices;
-// `masks`: 4 x refit_capacity() 64-bit words, a 256-bit pixel mask per entry; `counts`:
-// 4 words, zeroed here, counts[1] = listed pixels), then for MIXED an FP64 pass over those
-// pixels.  FP64: one tiled FP64 pass over every pixel.  `events` (optional, 3 entries)
-// are recorded before the fitting pass, after it, and after the recomputation pass.
-hipError_t launch_fit(const FitDesc& d, uint32_t* entries, uint64_t* masks, uint32_t* counts,
-                      hipStream_t stream, hipEvent_t* events = nullptr);
+// List of the pixels whose FP32 fit is to be recomputed in FP64 (device memory).  The
+// FP32 pass appends one entry per tile holding such pixels; the FP64 pass takes the
+// listed pixels by rank, so its work does not depend on how they cluster in tiles.
+struct RefitList {
+    uint32_t* entries;   // per entry: (frame << 24) | tile index within the frame
+    uint32_t* ranks;     // per entry: number of pixels listed in the entries before it
+    uint64_t* masks;     // 4 words per entry: the listed pixels (bit t = thread t of the tile)
+    uint32_t* counts;    // 4 words, 8-byte aligned, zeroed by every launch: [0] listed
+                         // pixels and [1] entries (one 64-bit counter, low word first),
+                         // [2] next tile of a batched FP32 pass, [3] next rank of the FP64 pass
+};
 
-// Tile entries needed for a width x height frame with tiles tile_w wide (masks: 4x).
+// Bytes of entries + ranks + masks for `tiles` entries, and the list carved out of them.
+size_t refit_list_bytes(int64_t tiles);
+RefitList refit_list(void* storage, int64_t tiles, uint32_t* counts);
+
+// Enqueues the whole fit of one frame on `stream`.  MIXED / FP32: a tiled FP32 pass
+// (MIXED: it lists the pixels whose fit is unreliable instead of storing them; the list
+// needs refit_capacity() entries), then for MIXED a persistent FP64 pass of `workgroups`
+// workgroups over the listed pixels.  FP64: one tiled FP64 pass over every pixel.
+// `events` (optional, 3 entries) are recorded before the FP32 pass, after it, and after
+// the FP64 pass.
+hipError_t launch_fit(const FitDesc& d, const RefitList& list, int workgroups, hipStream_t stream,
+                      hipEvent_t* events = nullptr);
+
+// Tile entries needed for a width x height frame with tiles tile_w wide.
 int64_t refit_capacity(int width, int height, int tile_w);
 bool valid_tile_width(int tile_w);
 
 // Enqueues the fit of a batch of frames: `frames` (device, FP32 MIXED/FP32 descriptors,
 // ordered by decreasing work per tile), `first_tile` (device, n + 1 prefix sums of the
-// frames' tile counts), `header` (device: [0] = n frames, [1] = 1 to recompute listed
-// pixels in FP64), all read when the kernels run, so the same launches can be captured
-// once and replayed with new contents.  One persistent FP32 pass of `workgroups`
-// workgroups over all tiles, then one persistent FP64 pass over the listed tiles.
-// Entry capacity: first_tile[n] (masks 4x); at most 256 frames.
+// frames' tile counts), `header` (device: [0] = n frames), all read when the kernels run,
+// so the same launches can be captured once and replayed with new contents.  One
+// persistent FP32 pass of `workgroups` workgroups over all tiles, then one persistent FP64
+// pass over the listed pixels of all frames.  List capacity: first_tile[n] entries; at
+// most 256 frames.
 hipError_t launch_fit_batch(const FitDesc* frames, const uint32_t* first_tile,
-                            const uint32_t* header, int workgroups, uint32_t* entries,
-                            uint64_t* masks, uint32_t* counts, hipStream_t stream,
-                            hipEvent_t* events = nullptr);
+                            const uint32_t* header, int workgroups, const RefitList& list,
+                            hipStream_t stream, hipEvent_t* events = nullptr);
 
 // Dynamic LDS of the batched kernels (largest tile shape at the largest radius).
 size_t batch_lds_bytes();

@@ -38,6 +38,9 @@ constexpr int kTileW = 16;
 #ifndef QC_F32_WAVES_PER_EU
 #define QC_F32_WAVES_PER_EU 4
 #endif
+#ifndef QC_F64_WAVES_PER_EU
+#define QC_F64_WAVES_PER_EU 4
+#endif
 
 // ---------------------------------------------------------------------------- scalars
 template <typename T> __device__ __forceinline__ T fmaT(T a, T b, T c);
@@ -81,6 +84,32 @@ struct LdsSource {
     const float2* centre;   // entry of the pixel itself
     int pitch;              // entries per LDS row
     __device__ __forceinline__ LdsRow row(int dv) const { return LdsRow{centre + dv * pitch}; }
+};
+// Neighbourhood read straight from the depth image (L2-resident), with the same (D, c)
+// pairs as the LDS copy.
+struct GlobalRow {
+    const char* row;   // depth row y (unused when y is outside the image)
+    int x, width, format;
+    bool inside;       // 0 <= y < height
+    __device__ __forceinline__ float2 operator[](int du) const {
+        const int xi = x + du;
+        if (!inside || xi < 0 || xi >= width) return make_float2(0.f, INFINITY);
+        float z;
+        if (format == 0) z = static_cast<float>(reinterpret_cast<const uint16_t*>(row)[xi]);
+        else if (format == 1) z = __half2float(reinterpret_cast<const __half*>(row)[xi]);
+        else z = reinterpret_cast<const float*>(row)[xi];
+        const bool ok = z > 0.f && z <= 3.0e38f;
+        return make_float2(ok ? z : 0.f, ok ? 1.f : INFINITY);
+    }
+};
+struct GlobalSource {
+    const char* depth;
+    int64_t pitch;
+    int width, height, format, u, v;
+    __device__ __forceinline__ GlobalRow row(int dv) const {
+        const int y = v + dv;
+        return GlobalRow{depth + static_cast<int64_t>(y) * pitch, u, width, format, y >= 0 && y < height};
+    }
 };
 // ---------------------------------------------------------------------------- one pixel
 template <typename Real>
@@ -464,15 +493,6 @@ __device__ __forceinline__ void store_pixel(const FitDesc& d, int64_t idx, const
 }
 
 // ---------------------------------------------------------------------------- kernels
-// Recomputation list and work counters.  counts[0]: listed tiles, counts[1]: listed
-// pixels, counts[2]: next tile of a batched fitting pass, counts[3]: next listed tile of a
-// batched recomputation pass.  An entry is (frame << 24) | tile index in its frame.
-struct TileList {
-    uint32_t* entries;
-    uint64_t* masks;     // 4 words (256 pixel bits) per entry
-    uint32_t* counts;
-};
-
 __global__ void zero_counts(uint32_t* counts) {
     if (threadIdx.x < 4) counts[threadIdx.x] = 0u;
 }
@@ -502,11 +522,12 @@ __device__ __forceinline__ int tiles_across(const FitDesc& d) {
 }
 
 // One tile of tw x (blockDim.x / tw) pixels, halo staged in LDS, one lane per pixel.  In
-// FP32 (MIXED / FP32) a tile holding unreliable fits is listed once with a 256-bit mask of
-// those pixels (bit t = thread t = pixel (t % tw, t / tw)).
+// MIXED precision the pixels whose FP32 fit is unreliable are not stored but listed: one
+// list entry for the tile with a 256-bit mask of them (bit t = thread t = pixel
+// (t % tw, t / tw)) and the rank of its first listed pixel.
 template <typename Real, int R>
 __device__ __forceinline__ void fit_tile_body(const FitDesc& d, int tx, int ty, uint32_t frame,
-                                              const TileList& list) {
+                                              const RefitList& list) {
     extern __shared__ float2 tile[];
     __shared__ uint64_t wave_masks[4];
     const int tw = d.tile_w, th = blockDim.x / tw;
@@ -515,29 +536,38 @@ __device__ __forceinline__ void fit_tile_body(const FitDesc& d, int tx, int ty, 
     stage_region(d, tile, tx * tw - halo, ty * th - halo, pitch, th + 2 * halo);
     const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
     const int u = tx * tw + lx, v = ty * th + ly;
+    const bool mixed = sizeof(Real) == 4 && d.precision == 0;
     bool recompute = false;
     if (u < d.width && v < d.height) {
         const float2* centre = tile + (ly + halo) * pitch + (lx + halo);
         const PixelFit<Real> r = !present(*centre)
             ? missing_pixel<Real>()
             : fit_pixel<Real, R>(d, LdsSource{centre, pitch}, u, v, centre->x, d.residual != nullptr);
-        store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
-        recompute = (r.flags & kFlagIll) != 0;
+        recompute = mixed && (r.flags & kFlagIll) != 0;
+        if (!recompute) store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
     }
     if constexpr (sizeof(Real) == 4) {
-        if (d.precision != 2) {
+        if (mixed) {
             const uint64_t mask = __ballot(recompute);
             if ((threadIdx.x % 64) == 0) wave_masks[threadIdx.x / 64] = mask;
             __syncthreads();
             if (threadIdx.x == 0) {
-                uint64_t m[4] = {0, 0, 0, 0};
-                for (int w = 0; w < static_cast<int>(blockDim.x / 64); ++w) m[w] = wave_masks[w];
-                if ((m[0] | m[1] | m[2] | m[3]) != 0) {
-                    const uint32_t slot = atomicAdd(&list.counts[0], 1u);
+                uint64_t m[4];
+                uint32_t n = 0;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    m[w] = wave_masks[w];
+                    n += static_cast<uint32_t>(__popcll(m[w]));
+                }
+                if (n != 0) {
+                    // one 64-bit add takes the entry slot (high word) and the rank (low word)
+                    const unsigned long long old = atomicAdd(
+                        reinterpret_cast<unsigned long long*>(list.counts), (1ull << 32) | n);
+                    const uint32_t slot = static_cast<uint32_t>(old >> 32);
                     list.entries[slot] = (frame << 24) | static_cast<uint32_t>(ty * tiles_across(d) + tx);
+                    list.ranks[slot] = static_cast<uint32_t>(old);
+#pragma unroll
                     for (int w = 0; w < 4; ++w) list.masks[4 * slot + w] = m[w];
-                    atomicAdd(&list.counts[1], static_cast<uint32_t>(__popcll(m[0]) + __popcll(m[1]) +
-                                                                     __popcll(m[2]) + __popcll(m[3])));
                 }
             }
             __syncthreads();   // wave_masks is reused by the next tile of a persistent loop
@@ -558,14 +588,14 @@ __device__ __forceinline__ void with_radius(int r, F&& f) {
 // FP32 pass over one frame: one 256-lane workgroup per tile.
 template <int R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))
-void fit_tile_f32(FitDesc d, TileList list) {
+void fit_tile_f32(FitDesc d, RefitList list) {
     fit_tile_body<float, R>(d, blockIdx.x, blockIdx.y, 0u, list);
 }
 
 // FP64 pass over every pixel of one frame: 16x4 tiles.
 template <int R>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
-void fit_tile_f64(FitDesc d, TileList list) {
+void fit_tile_f64(FitDesc d, RefitList list) {
     fit_tile_body<double, R>(d, blockIdx.x, blockIdx.y, 0u, list);
 }
 
@@ -575,7 +605,7 @@ void fit_tile_f64(FitDesc d, TileList list) {
 // next tile number from counts[2] until none is left, so all frames share one launch.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))
 void fit_batch_f32(const FitDesc* frames, const uint32_t* first_tile, const uint32_t* header,
-                   TileList list) {
+                   RefitList list) {
     __shared__ uint32_t next;
     const uint32_t nf = header[0];
     if (nf == 0) return;
@@ -602,6 +632,13 @@ void fit_batch_f32(const FitDesc* frames, const uint32_t* first_tile, const uint
     }
 }
 
+// ---------------------------------------------------------------------------- FP64 pass
+// Each listed pixel is fitted by a group of kRefitLanes lanes that split its window rows;
+// a wave takes 64 / kRefitLanes consecutive ranks at a time from counts[3], so the work is
+// shared out pixel by pixel whatever the tiles the pixels came from.
+constexpr int kRefitLanes = 4;
+constexpr uint32_t kRanksPerWave = 64 / kRefitLanes;
+
 // Position (0..63) of the n-th set bit (n counted from 0) of m; m has more than n bits.
 __device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
     int pos = 0;
@@ -620,84 +657,97 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
     return pos;
 }
 
-// FP64 recomputation of the listed pixels of one listed tile by a 256-lane workgroup:
-// tile plus halo staged in LDS; each listed pixel is fitted by a group of kRefitLanes
-// lanes that split its window rows (the listed pixels are few, so one lane per pixel
-// would leave most SIMDs idle); the tile's listed pixels are taken 256/kRefitLanes at a
-// time in mask order.
-constexpr int kRefitLanes = 4;
+// The listed pixel of rank q < listed pixels: its entry (the last whose rank is <= q)
+// and its thread within the entry's tile.
+__device__ __forceinline__ void listed_pixel(const RefitList& list, uint32_t entries, uint32_t q,
+                                             uint32_t& entry, int& thread) {
+    uint32_t lo = 0, hi = entries - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) / 2;
+        if (list.ranks[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    entry = list.entries[lo];
+    int n = static_cast<int>(q - list.ranks[lo]);
+    const uint64_t* m = list.masks + 4 * static_cast<size_t>(lo);
+    int w = 0;
+    for (; w < 3; ++w) {
+        const int c = __popcll(m[w]);
+        if (n < c) break;
+        n -= c;
+    }
+    thread = w * 64 + nth_set_bit(m[w], n);
+}
+
+// The next kRanksPerWave ranks for this wave (the same value in every lane).
+__device__ __forceinline__ uint32_t next_ranks(uint32_t* counter) {
+    uint32_t base = 0;
+    if ((threadIdx.x % 64) == 0) base = atomicAdd(counter, kRanksPerWave);
+    return __builtin_amdgcn_readfirstlane(base);
+}
 
 template <int R>
-__device__ __forceinline__ void refit_tile_body(const FitDesc& d, uint32_t tile_index,
-                                                const uint64_t* mask_words) {
-    extern __shared__ float2 tile[];
+__device__ __forceinline__ void refit_pixel(const FitDesc& d, uint32_t tile, int thread,
+                                            const LaneGroup<kRefitLanes>& grp) {
     const int tw = d.tile_w, th = 256 / tw;
     const int across = tiles_across(d);
-    const int bx = static_cast<int>(tile_index % across) * tw;
-    const int by = static_cast<int>(tile_index / across) * th;
-    const int halo = max(R, d.normal_radius);
-    const int pitch = tw + 2 * halo;
-    stage_region(d, tile, bx - halo, by - halo, pitch, th + 2 * halo);
-    const int group = threadIdx.x / kRefitLanes;
-    const LaneGroup<kRefitLanes> grp{static_cast<int>(threadIdx.x % kRefitLanes)};
-    uint64_t m[4];
-    int total = 0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        m[w] = mask_words[w];
-        total += __popcll(m[w]);
-    }
-    for (int base = 0; base < total; base += 256 / kRefitLanes) {
-        const int t = base + group;   // rank of this group's pixel among the listed ones
-        if (t < total) {
-            int before = 0, word = 0, rank = 0;
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const int c = __popcll(m[w]);
-                if (t >= before && t < before + c) {
-                    word = w;
-                    rank = t - before;
-                }
-                before += c;
-            }
-            const int thread = word * 64 + nth_set_bit(m[word], rank);
-            const int lx = thread % tw, ly = thread / tw;
-            const int u = bx + lx, v = by + ly;
-            const float2* centre = tile + (ly + halo) * pitch + (lx + halo);
-            const PixelFit<double> r = fit_pixel<double, R, kRefitLanes>(
-                d, LdsSource{centre, pitch}, u, v, centre->x, d.residual != nullptr, grp);
-            if (grp.part == 0) store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
+    const int u = static_cast<int>(tile % across) * tw + thread % tw;
+    const int v = static_cast<int>(tile / across) * th + thread / tw;
+    const float Dc = sample_or_missing(d, u, v).x;   // a listed pixel has its depth
+    const PixelFit<double> r = fit_pixel<double, R, kRefitLanes>(
+        d, GlobalSource{static_cast<const char*>(d.depth), d.pitch, d.width, d.height, d.format, u, v},
+        u, v, Dc, d.residual != nullptr, grp);
+    if (grp.part == 0) store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
+}
+
+// FP64 pass over the listed pixels of one frame (persistent: waves loop until the ranks
+// run out).
+template <int R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
+void refit_f64(FitDesc d, RefitList list) {
+    const uint32_t pixels = list.counts[0], entries = list.counts[1];
+    const int lane = threadIdx.x % 64;
+    const LaneGroup<kRefitLanes> grp{lane % kRefitLanes};
+    for (;;) {
+        const uint32_t base = next_ranks(&list.counts[3]);
+        if (base >= pixels) break;
+        const uint32_t q = base + static_cast<uint32_t>(lane / kRefitLanes);
+        if (q < pixels) {
+            uint32_t entry;
+            int thread;
+            listed_pixel(list, entries, q, entry, thread);
+            refit_pixel<R>(d, entry & 0xffffffu, thread, grp);
         }
     }
-    __syncthreads();   // the next entry re-stages the LDS region
 }
 
-// FP64 recomputation for one frame: workgroups stride over the listed tiles.
-template <int R>
-__global__ __launch_bounds__(256) void refit_tiles_f64(FitDesc d, TileList list) {
-    const uint32_t n = list.counts[0];
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
-        refit_tile_body<R>(d, list.entries[i] & 0xffffffu, list.masks + 4 * i);
-}
-
-// FP64 recomputation for a batch (header[1] != 0): workgroups take listed tiles from
-// counts[3].
-__global__ __launch_bounds__(256) void refit_batch_f64(const FitDesc* frames, const uint32_t* header,
-                                                       TileList list) {
-    __shared__ uint32_t next;
-    if (header[1] == 0) return;
-    const uint32_t n = list.counts[0];
+// FP64 pass over the listed pixels of a batch.  The ranks a wave takes may span frames;
+// the wave then handles one frame at a time, so that the frame's descriptor and window
+// radius stay uniform.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
+void refit_batch_f64(const FitDesc* frames, RefitList list) {
+    const uint32_t pixels = list.counts[0], entries = list.counts[1];
+    const int lane = threadIdx.x % 64;
+    const LaneGroup<kRefitLanes> grp{lane % kRefitLanes};
     for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(&list.counts[3], 1u);
-        __syncthreads();
-        const uint32_t i = __builtin_amdgcn_readfirstlane(next);
-        __syncthreads();
-        if (i >= n) break;
-        const uint32_t e = __builtin_amdgcn_readfirstlane(list.entries[i]);
-        const FitDesc d = frames[e >> 24];
-        with_radius(d.radius, [&](auto rc) {
-            refit_tile_body<decltype(rc)::value>(d, e & 0xffffffu, list.masks + 4 * i);
-        });
+        const uint32_t base = next_ranks(&list.counts[3]);
+        if (base >= pixels) break;
+        const uint32_t q = base + static_cast<uint32_t>(lane / kRefitLanes);
+        bool pending = q < pixels;
+        uint32_t entry = 0;
+        int thread = 0;
+        if (pending) listed_pixel(list, entries, q, entry, thread);
+        for (;;) {
+            const uint64_t waiting = __ballot(pending);
+            if (waiting == 0) break;
+            const uint32_t f = __builtin_amdgcn_readlane(entry >> 24, __ffsll(static_cast<long long>(waiting)) - 1);
+            if (pending && (entry >> 24) == f) {
+                const FitDesc d = frames[f];
+                with_radius(d.radius, [&](auto rc) {
+                    refit_pixel<decltype(rc)::value>(d, entry & 0xffffffu, thread, grp);
+                });
+                pending = false;
+            }
+        }
     }
 }
 
@@ -706,7 +756,8 @@ size_t lds_bytes(int tile_w, int tile_h, int halo) {
 }
 
 template <int R>
-hipError_t launch_radius(const FitDesc& d, const TileList& list, hipStream_t st, hipEvent_t* ev) {
+hipError_t launch_radius(const FitDesc& d, const RefitList& list, int workgroups, hipStream_t st,
+                         hipEvent_t* ev) {
     const int halo = R > d.normal_radius ? R : d.normal_radius;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
@@ -727,10 +778,7 @@ hipError_t launch_radius(const FitDesc& d, const TileList& list, hipStream_t st,
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
     if (d.precision == 0) {
-        // one workgroup per listed tile in the worst case, capped; each loops over entries
-        const uint32_t tiles = grid.x * grid.y;
-        const uint32_t nwg = tiles < 4096u ? tiles : 4096u;
-        hipLaunchKernelGGL(refit_tiles_f64<R>, dim3(nwg), dim3(256), lds, st, d, list);
+        hipLaunchKernelGGL(refit_f64<R>, dim3(workgroups), dim3(256), 0, st, d, list);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
@@ -738,10 +786,10 @@ hipError_t launch_radius(const FitDesc& d, const TileList& list, hipStream_t st,
 }
 
 template <int... Rs>
-hipError_t dispatch_radius(int r, const FitDesc& d, const TileList& list, hipStream_t st,
-                           hipEvent_t* ev, std::integer_sequence<int, Rs...>) {
+hipError_t dispatch_radius(int r, const FitDesc& d, const RefitList& list, int workgroups,
+                           hipStream_t st, hipEvent_t* ev, std::integer_sequence<int, Rs...>) {
     hipError_t e = hipErrorInvalidValue;
-    (void)((r == Rs + 1 ? (e = launch_radius<Rs + 1>(d, list, st, ev), true) : false) || ...);
+    (void)((r == Rs + 1 ? (e = launch_radius<Rs + 1>(d, list, workgroups, st, ev), true) : false) || ...);
     return e;
 }
 
@@ -756,15 +804,28 @@ bool valid_tile_width(int tile_w) {
     return tile_w == 8 || tile_w == 16 || tile_w == 32 || tile_w == 64;
 }
 
-hipError_t launch_fit(const FitDesc& d, uint32_t* entries, uint64_t* masks, uint32_t* counts,
-                      hipStream_t stream, hipEvent_t* events) {
-    const TileList list{entries, masks, counts};
+size_t refit_list_bytes(int64_t tiles) {
+    return static_cast<size_t>(tiles) * (4 * sizeof(uint64_t) + 2 * sizeof(uint32_t));
+}
+
+RefitList refit_list(void* storage, int64_t tiles, uint32_t* counts) {
+    char* p = static_cast<char*>(storage);
+    RefitList l;
+    l.masks = reinterpret_cast<uint64_t*>(p);
+    l.entries = reinterpret_cast<uint32_t*>(p + 4 * sizeof(uint64_t) * static_cast<size_t>(tiles));
+    l.ranks = l.entries + tiles;
+    l.counts = counts;
+    return l;
+}
+
+hipError_t launch_fit(const FitDesc& d, const RefitList& list, int workgroups, hipStream_t stream,
+                      hipEvent_t* events) {
     if (d.precision != 2) {
-        hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, counts);
+        hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, list.counts);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return dispatch_radius(d.radius, d, list, stream, events,
+    return dispatch_radius(d.radius, d, list, workgroups, stream, events,
                            std::make_integer_sequence<int, kMaxRadius>{});
 }
 
@@ -779,12 +840,10 @@ size_t batch_lds_bytes() {
 }
 
 hipError_t launch_fit_batch(const FitDesc* frames, const uint32_t* first_tile,
-                            const uint32_t* header, int workgroups, uint32_t* entries,
-                            uint64_t* masks, uint32_t* counts, hipStream_t stream,
-                            hipEvent_t* events) {
-    const TileList list{entries, masks, counts};
+                            const uint32_t* header, int workgroups, const RefitList& list,
+                            hipStream_t stream, hipEvent_t* events) {
     hipError_t e;
-    hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, counts);
+    hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, list.counts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const size_t lds = batch_lds_bytes();
     if (events && (e = hipEventRecord(events[0], stream)) != hipSuccess) return e;
@@ -792,8 +851,7 @@ hipError_t launch_fit_batch(const FitDesc* frames, const uint32_t* first_tile,
                        header, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (events && (e = hipEventRecord(events[1], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(refit_batch_f64, dim3(workgroups), dim3(256), lds, stream, frames, header,
-                       list);
+    hipLaunchKernelGGL(refit_batch_f64, dim3(workgroups), dim3(256), 0, stream, frames, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (events && (e = hipEventRecord(events[2], stream)) != hipSuccess) return e;
     return hipSuccess;

@@ -19,22 +19,21 @@
 
 namespace {
 
-// Host staging of one batch: descriptors, tile prefix sums and a two-word header, copied
-// to the device by the first node of the batch graph.
+// Host staging of one batch: descriptors, tile prefix sums and a header, copied to the
+// device by the first node of the batch graph.
 struct BatchStaging {
     qc::FitDesc frames[QC_MAX_BATCH];
     uint32_t first_tile[QC_MAX_BATCH + 1];
-    uint32_t header[2];   // [0] frames, [1] recompute listed pixels in FP64
+    uint32_t header[1];   // [0] frames
 };
 
 // One of the two batches a context may have in flight.
 struct BatchSlot {
     BatchStaging* host = nullptr;   // pinned
     BatchStaging* dev = nullptr;
-    uint32_t* entries = nullptr;
-    uint64_t* masks = nullptr;
+    void* list = nullptr;           // refit list storage for `capacity` entries
     uint32_t* counts = nullptr;
-    int64_t capacity = 0;           // tile entries
+    int64_t capacity = 0;           // refit list entries
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;      // recorded after the slot's last use
@@ -49,8 +48,7 @@ struct qc_context {
     int device = 0;
     int cus = 0;
     int last_hip_error = 0;
-    uint32_t* refit_entries = nullptr; // device, capacity tile indices
-    uint64_t* refit_masks = nullptr;   // device, 4 x capacity words (256-bit pixel masks)
+    void* refit_storage = nullptr;     // device, refit list for `capacity` entries
     uint32_t* refit_counts = nullptr;  // device, 4 counters
     int64_t capacity = 0;
     hipStream_t last_stream = nullptr;
@@ -158,25 +156,16 @@ qc::FitDesc make_desc(const qc_frame* frame, const qc_params* params, const qc_o
 qc_status ensure_capacity(qc_context* ctx, int64_t entries) {
     if (ctx->capacity >= entries) return QC_OK;
     hipError_t e;
-    if (ctx->refit_entries) {
-        // the previous lists may still be in use by enqueued work
+    if (ctx->refit_storage) {
+        // the previous list may still be in use by enqueued work
         if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(ctx, e);
-        (void)hipFree(ctx->refit_entries);
-        (void)hipFree(ctx->refit_masks);
-        ctx->refit_entries = nullptr;
-        ctx->refit_masks = nullptr;
+        (void)hipFree(ctx->refit_storage);
+        ctx->refit_storage = nullptr;
         ctx->capacity = 0;
     }
     void* p = nullptr;
-    void* q = nullptr;
-    if ((e = hipMalloc(&p, sizeof(uint32_t) * static_cast<size_t>(entries))) != hipSuccess)
-        return hip_fail(ctx, e);
-    if ((e = hipMalloc(&q, 4 * sizeof(uint64_t) * static_cast<size_t>(entries))) != hipSuccess) {
-        (void)hipFree(p);
-        return hip_fail(ctx, e);
-    }
-    ctx->refit_entries = static_cast<uint32_t*>(p);
-    ctx->refit_masks = static_cast<uint64_t*>(q);
+    if ((e = hipMalloc(&p, qc::refit_list_bytes(entries))) != hipSuccess) return hip_fail(ctx, e);
+    ctx->refit_storage = p;
     ctx->capacity = entries;
     return QC_OK;
 }
@@ -184,12 +173,10 @@ qc_status ensure_capacity(qc_context* ctx, int64_t entries) {
 void free_slot(BatchSlot& s) {
     if (s.exec) (void)hipGraphExecDestroy(s.exec);
     if (s.graph) (void)hipGraphDestroy(s.graph);
-    if (s.entries) (void)hipFree(s.entries);
-    if (s.masks) (void)hipFree(s.masks);
+    if (s.list) (void)hipFree(s.list);
     s.exec = nullptr;
     s.graph = nullptr;
-    s.entries = nullptr;
-    s.masks = nullptr;
+    s.list = nullptr;
     s.capacity = 0;
 }
 
@@ -215,13 +202,8 @@ qc_status prepare_slot(qc_context* ctx, BatchSlot& s, int64_t entries) {
     free_slot(s);
     const int64_t cap = std::max<int64_t>(entries, 1 << 16);
     void* p = nullptr;
-    void* q = nullptr;
-    if ((e = hipMalloc(&p, sizeof(uint32_t) * static_cast<size_t>(cap))) != hipSuccess)
-        return hip_fail(ctx, e);
-    s.entries = static_cast<uint32_t*>(p);
-    if ((e = hipMalloc(&q, 4 * sizeof(uint64_t) * static_cast<size_t>(cap))) != hipSuccess)
-        return hip_fail(ctx, e);
-    s.masks = static_cast<uint64_t*>(q);
+    if ((e = hipMalloc(&p, qc::refit_list_bytes(cap))) != hipSuccess) return hip_fail(ctx, e);
+    s.list = p;
     s.capacity = cap;
     hipStream_t cs = ctx->capture_stream;
     if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
@@ -229,7 +211,7 @@ qc_status prepare_slot(qc_context* ctx, BatchSlot& s, int64_t entries) {
     hipError_t le = hipMemcpyAsync(s.dev, s.host, sizeof(BatchStaging), hipMemcpyHostToDevice, cs);
     if (le == hipSuccess)
         le = qc::launch_fit_batch(s.dev->frames, s.dev->first_tile, s.dev->header, 4 * ctx->cus,
-                                  s.entries, s.masks, s.counts, cs);
+                                  qc::refit_list(s.list, s.capacity, s.counts), cs);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
     if (le != hipSuccess) {
@@ -302,8 +284,7 @@ qc_status qc_destroy(qc_context* ctx) {
     if (!ctx) return QC_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    if (ctx->refit_entries) (void)hipFree(ctx->refit_entries);
-    if (ctx->refit_masks) (void)hipFree(ctx->refit_masks);
+    if (ctx->refit_storage) (void)hipFree(ctx->refit_storage);
     if (ctx->refit_counts) (void)hipFree(ctx->refit_counts);
     for (hipEvent_t ev : ctx->pending) (void)hipEventDestroy(ev);
     for (BatchSlot& s : ctx->slots) {
@@ -338,8 +319,8 @@ qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params
             if ((e = hipEventCreate(&x)) != hipSuccess) return hip_fail(ctx, e);
         ctx->pending.insert(ctx->pending.end(), ev, ev + 3);
     }
-    if ((e = qc::launch_fit(d, ctx->refit_entries, ctx->refit_masks, ctx->refit_counts, s,
-                            ctx->timing ? ev : nullptr)) != hipSuccess)
+    const qc::RefitList list = qc::refit_list(ctx->refit_storage, ctx->capacity, ctx->refit_counts);
+    if ((e = qc::launch_fit(d, list, 4 * ctx->cus, s, ctx->timing ? ev : nullptr)) != hipSuccess)
         return hip_fail(ctx, e);
     ctx->last_stream = s;
     ctx->last_precision = params->precision;
@@ -390,7 +371,6 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
     std::memcpy(s.host->frames, descs.data(), sizeof(qc::FitDesc) * n);
     std::memcpy(s.host->first_tile, first.data(), sizeof(uint32_t) * (n + 1));
     s.host->header[0] = static_cast<uint32_t>(n);
-    s.host->header[1] = prec == QC_PREC_MIXED ? 1u : 0u;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     if (ctx->timing) {
         // timed batches run eagerly so that the two passes can be bracketed separately
@@ -400,7 +380,7 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
         ctx->pending.insert(ctx->pending.end(), ev, ev + 3);
         if ((e = hipMemcpyAsync(s.dev, s.host, sizeof(BatchStaging), hipMemcpyHostToDevice, hs)) != hipSuccess ||
             (e = qc::launch_fit_batch(s.dev->frames, s.dev->first_tile, s.dev->header, 4 * ctx->cus,
-                                      s.entries, s.masks, s.counts, hs, ev)) != hipSuccess)
+                                      qc::refit_list(s.list, s.capacity, s.counts), hs, ev)) != hipSuccess)
             return hip_fail(ctx, e);
     } else if ((e = hipGraphLaunch(s.exec, hs)) != hipSuccess) {
         return hip_fail(ctx, e);
@@ -490,10 +470,10 @@ qc_status qc_last_refit_count(qc_context* ctx, uint32_t* count) {
     hipError_t e;
     if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
     if ((e = hipStreamSynchronize(ctx->last_stream)) != hipSuccess) return hip_fail(ctx, e);
-    uint32_t counts[2] = {0, 0};
+    uint32_t counts[2] = {0, 0};   // [0] listed pixels, [1] list entries
     if ((e = hipMemcpy(counts, ctx->refit_counts, sizeof counts, hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(ctx, e);
-    *count = counts[1];
+    *count = counts[0];
     return QC_OK;
 }
 
