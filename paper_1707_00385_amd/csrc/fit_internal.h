@@ -33,10 +33,14 @@ struct RefitList {
     uint32_t* entries;   // per entry: (frame << 24) | tile index within the frame
     uint32_t* ranks;     // per entry: number of pixels listed in the entries before it
     uint64_t* masks;     // 4 words per entry: the listed pixels (bit t = thread t of the tile)
-    uint32_t* counts;    // 4 words, 8-byte aligned, zeroed by every launch: [0] listed
-                         // pixels and [1] entries (one 64-bit counter, low word first),
-                         // [2] next tile of a batched FP32 pass, [3] next rank of the FP64 pass
+    uint32_t* counts;    // kCountWords words, 8-byte aligned, zeroed by every launch:
+                         // [0] ranks handed out (each entry's pixel count rounded up to a
+                         // multiple of 16, so that 16 consecutive ranks never span two
+                         // entries) and [1] entries (one 64-bit counter, low word first),
+                         // [2] next tile of a batched FP32 pass, [3] next rank of the FP64
+                         // pass, [4] listed pixels
 };
+constexpr int kCountWords = 8;
 
 // Bytes of entries + ranks + masks for `tiles` entries, and the list carved out of them.
 size_t refit_list_bytes(int64_t tiles);
@@ -44,11 +48,11 @@ RefitList refit_list(void* storage, int64_t tiles, uint32_t* counts);
 
 // Enqueues the whole fit of one frame on `stream`.  MIXED / FP32: a tiled FP32 pass
 // (MIXED: it lists the pixels whose fit is unreliable instead of storing them; the list
-// needs refit_capacity() entries), then for MIXED a persistent FP64 pass of `workgroups`
-// workgroups over the listed pixels.  FP64: one tiled FP64 pass over every pixel.
+// needs refit_capacity() entries), then for MIXED a persistent FP64 pass sized for `cus`
+// compute units over the listed pixels.  FP64: one tiled FP64 pass over every pixel.
 // `events` (optional, 3 entries) are recorded before the FP32 pass, after it, and after
 // the FP64 pass.
-hipError_t launch_fit(const FitDesc& d, const RefitList& list, int workgroups, hipStream_t stream,
+hipError_t launch_fit(const FitDesc& d, const RefitList& list, int cus, hipStream_t stream,
                       hipEvent_t* events = nullptr);
 
 // Tile entries needed for a width x height frame with tiles tile_w wide.

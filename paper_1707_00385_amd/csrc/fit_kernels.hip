@@ -39,7 +39,10 @@ constexpr int kTileW = 16;
 #define QC_F32_WAVES_PER_EU 4
 #endif
 #ifndef QC_F64_WAVES_PER_EU
-#define QC_F64_WAVES_PER_EU 4
+#define QC_F64_WAVES_PER_EU 3
+#endif
+#ifndef QC_F64_UNROLL
+#define QC_F64_UNROLL 3
 #endif
 
 // ---------------------------------------------------------------------------- scalars
@@ -50,7 +53,15 @@ template <> __device__ __forceinline__ double fmaT(double a, double b, double c)
 // 1/sqrt(x) with 1/sqrt(+inf) = 0 (the weight of a missing neighbour).
 template <typename T> __device__ __forceinline__ T rsqrtT(T x);
 template <> __device__ __forceinline__ float rsqrtT(float x) { return __builtin_amdgcn_rsqf(x); }
-template <> __device__ __forceinline__ double rsqrtT(double x) { return isinf(x) ? 0.0 : rsqrt(x); }
+// FP64: the hardware estimate y refined by the second-order expansion of (1 - e)^(-1/2),
+// e = 1 - x y^2, i.e. y (1 + e/2 + 3 e^2 / 8); written without branches so that it stays
+// in the straight-line code of the window loop.
+template <> __device__ __forceinline__ double rsqrtT(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = __builtin_fma(-x * y, y, 1.0);
+    const double r = __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+    return x < INFINITY ? r : 0.0;
+}
 
 template <typename T> __device__ __forceinline__ T sqrtT(T x) { return sqrt(x); }
 template <typename T> __device__ __forceinline__ T sinT(T x) { return sin(x); }
@@ -86,19 +97,26 @@ struct LdsSource {
     __device__ __forceinline__ LdsRow row(int dv) const { return LdsRow{centre + dv * pitch}; }
 };
 // Neighbourhood read straight from the depth image (L2-resident), with the same (D, c)
-// pairs as the LDS copy.
+// pairs as the LDS copy.  The read is branch-free, so that the window loop stays straight-
+// line code whose loads can be issued ahead: coordinates are clamped into the image, a
+// sample is read as two 16-bit halves (the second one 2 bytes on for F32, the same half
+// otherwise) and decoded by the format, and outside samples are marked missing afterwards.
 struct GlobalRow {
-    const char* row;   // depth row y (unused when y is outside the image)
-    int x, width, format;
-    bool inside;       // 0 <= y < height
+    const char* row;   // depth row clamped into the image
+    int x, wm1, shift, hi_off, format;
+    bool inside;       // the unclamped row lies in the image
     __device__ __forceinline__ float2 operator[](int du) const {
         const int xi = x + du;
-        if (!inside || xi < 0 || xi >= width) return make_float2(0.f, INFINITY);
-        float z;
-        if (format == 0) z = static_cast<float>(reinterpret_cast<const uint16_t*>(row)[xi]);
-        else if (format == 1) z = __half2float(reinterpret_cast<const __half*>(row)[xi]);
-        else z = reinterpret_cast<const float*>(row)[xi];
-        const bool ok = z > 0.f && z <= 3.0e38f;
+        const bool in = inside && static_cast<unsigned>(xi) <= static_cast<unsigned>(wm1);
+        const int xc = min(max(xi, 0), wm1);
+        const char* p = row + (static_cast<int64_t>(xc) << shift);
+        const uint32_t lo = *reinterpret_cast<const uint16_t*>(p);
+        const uint32_t hi = *reinterpret_cast<const uint16_t*>(p + hi_off);
+        const float zu = static_cast<float>(lo);
+        const float zh = __half2float(__ushort_as_half(static_cast<unsigned short>(lo)));
+        const float zf = __uint_as_float((hi << 16) | lo);
+        const float z = format == 0 ? zu : (format == 1 ? zh : zf);
+        const bool ok = in && z > 0.f && z <= 3.0e38f;   // excludes 0, negatives, inf and NaN
         return make_float2(ok ? z : 0.f, ok ? 1.f : INFINITY);
     }
 };
@@ -108,7 +126,9 @@ struct GlobalSource {
     int width, height, format, u, v;
     __device__ __forceinline__ GlobalRow row(int dv) const {
         const int y = v + dv;
-        return GlobalRow{depth + static_cast<int64_t>(y) * pitch, u, width, format, y >= 0 && y < height};
+        const int yc = min(max(y, 0), height - 1);
+        return GlobalRow{depth + static_cast<int64_t>(yc) * pitch, u, width - 1, format == 2 ? 2 : 1,
+                         format == 2 ? 2 : 0, format, static_cast<unsigned>(y) < static_cast<unsigned>(height)};
     }
 };
 // ---------------------------------------------------------------------------- one pixel
@@ -128,21 +148,47 @@ struct Geometry {
 // dv = -r + part, -r + part + NP, ..., and sum() adds a value over the group by an xor
 // butterfly, which leaves every lane of the group with the same bits (the additions are
 // the same pairs in the same order up to commutation).  NP = 1 is one lane per pixel.
+// Value of lane (this lane xor M) within its quad of four lanes (DPP quad permutation).
+template <int M>
+__device__ __forceinline__ int quad_xor(int v) {
+    constexpr int ctrl = M == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] / [2,3,0,1]
+    return __builtin_amdgcn_update_dpp(0, v, ctrl, 0xF, 0xF, false);
+}
+template <int M, typename T>
+__device__ __forceinline__ T lane_xor(T x) {
+    if constexpr (M < 4) {
+        if constexpr (sizeof(T) == 8) {
+            const uint64_t b = __builtin_bit_cast(uint64_t, x);
+            const uint32_t lo = static_cast<uint32_t>(quad_xor<M>(static_cast<int>(b)));
+            const uint32_t hi = static_cast<uint32_t>(quad_xor<M>(static_cast<int>(b >> 32)));
+            return __builtin_bit_cast(T, (static_cast<uint64_t>(hi) << 32) | lo);
+        } else {
+            return __builtin_bit_cast(T, quad_xor<M>(__builtin_bit_cast(int, x)));
+        }
+    } else {
+        return __shfl_xor(x, M);
+    }
+}
+
 template <int NP>
 struct LaneGroup {
     int part;
     template <typename T>
     __device__ __forceinline__ T sum(T x) const {
-        if constexpr (NP > 1) {
-#pragma unroll
-            for (int m = 1; m < NP; m <<= 1) x += __shfl_xor(x, m);
-        }
+        if constexpr (NP > 1) x += lane_xor<1>(x);
+        if constexpr (NP > 2) x += lane_xor<2>(x);
+        if constexpr (NP > 4) x += lane_xor<4>(x);
+        if constexpr (NP > 8) x += lane_xor<8>(x);
+        if constexpr (NP > 16) x += lane_xor<16>(x);
+        if constexpr (NP > 32) x += lane_xor<32>(x);
         return x;
     }
 };
 
 // Loops over this lane's window rows; RC > 0 fixes R at compile time.  A row is fully
-// unrolled for FP32 (U = 0); FP64 keeps it rolled (U = 1) to stay within the register file.
+// unrolled for FP32 (U = 0); FP64 unrolls it U neighbours at a time (U >= 2), so that the
+// dependency chains of several neighbours interleave, or keeps it rolled (U = 1), to stay
+// within the register file.
 template <int RC, int U, int NP, typename Src, typename F>
 __device__ __forceinline__ void for_window(const Src& src, int radius, const LaneGroup<NP>& grp,
                                            F&& f) {
@@ -153,6 +199,12 @@ __device__ __forceinline__ void for_window(const Src& src, int radius, const Lan
             auto row = src.row(dv);
 #pragma unroll
             for (int du = -RC; du <= RC; ++du) f(row[du], du, dv);
+        }
+    } else if constexpr (U >= 2) {
+        for (int dv = first; dv <= r; dv += NP) {
+            auto row = src.row(dv);
+#pragma unroll U
+            for (int du = -r; du <= r; ++du) f(row[du], du, dv);
         }
     } else {
         // rolled row: the next sample's LDS read is issued before this one is used
@@ -244,7 +296,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
         if (fp32) out.flags = kFlagIll;   // let FP64 decide
         return out;
     }
-    if (fp32 && !(det > Real(1e-4) * tr * tr)) ill = true;
+    if (fp32 && !(det > Real(1e-3) * tr * tr)) ill = true;
     const Real ia = (M11 * v0 - M01 * v1) / det;
     const Real ib = (M00 * v1 - M01 * v0) / det;
     const Real nsc = Real(1) / sqrtT(Real(1) + ia * ia + ib * ib);
@@ -252,7 +304,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
 
     // ---- enough neighbours for six parameters
     Real nfit = 0;
-    for_window<RC, sizeof(Real) == 8>(src, radius, grp,
+    for_window<RC, sizeof(Real) == 8 ? QC_F64_UNROLL : 0>(src, radius, grp,
                                       [&](float2 t, int, int) { nfit += present(t) ? Real(1) : Real(0); });
     nfit = grp.sum(nfit);
     if (nfit < Real(6)) return out;
@@ -291,7 +343,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
         Acc H33 = 0, H34 = 0, H35 = 0, H45 = 0, H55 = 0;
         Acc S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0;
         Acc G0 = 0, G1 = 0, G2 = 0, G3 = 0, G4 = 0, G5 = 0;
-        for_window<RC, sizeof(Real) == 8>(src, radius, grp, [&](float2 t, int du, int dv) {
+        for_window<RC, sizeof(Real) == 8 ? QC_F64_UNROLL : 0>(src, radius, grp, [&](float2 t, int du, int dv) {
             // s = R' m with m = (du D, dv D, D - Dc), as (R'x0 du + R'x1 dv) D + R'x2 (D - Dc)
             const Real D = Real(t.x);
             const Real dD = D - g.Dc;
@@ -444,7 +496,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
         }
         const Real Ah = Real(0.5) * A, Bh = Real(0.5) * B, Ch = Real(0.5) * C;
         Real sw = 0, swe = 0;
-        for_window<RC, sizeof(Real) == 8>(src, radius, grp, [&](float2 t, int du, int dv) {
+        for_window<RC, sizeof(Real) == 8 ? QC_F64_UNROLL : 0>(src, radius, grp, [&](float2 t, int du, int dv) {
             const Real D = Real(t.x), dD = D - g.Dc;
             const Real mx = Real(du) * D, my = Real(dv) * D;
             const Real sx = fmaT(Rp[0][0], mx, fmaT(Rp[0][1], my, Rp[0][2] * dD));
@@ -494,8 +546,13 @@ __device__ __forceinline__ void store_pixel(const FitDesc& d, int64_t idx, const
 
 // ---------------------------------------------------------------------------- kernels
 __global__ void zero_counts(uint32_t* counts) {
-    if (threadIdx.x < 4) counts[threadIdx.x] = 0u;
+    if (threadIdx.x < kCountWords) counts[threadIdx.x] = 0u;
 }
+
+// FP64 pass: each listed pixel is fitted by a group of kRefitLanes lanes that split its
+// window rows, so a wave takes kChunk listed pixels at a time.
+constexpr int kRefitLanes = 4;
+constexpr uint32_t kChunk = 64 / kRefitLanes;
 
 // Stages the depth samples of a (w + 2 halo) x (h + 2 halo) region whose top-left pixel
 // is (x0, y0) into LDS as (D, c) pairs.
@@ -560,9 +617,12 @@ __device__ __forceinline__ void fit_tile_body(const FitDesc& d, int tx, int ty, 
                     n += static_cast<uint32_t>(__popcll(m[w]));
                 }
                 if (n != 0) {
-                    // one 64-bit add takes the entry slot (high word) and the rank (low word)
+                    // one 64-bit add takes the entry slot (high word) and the rank (low
+                    // word); ranks advance by n rounded up to whole chunks
+                    const uint32_t padded = (n + kChunk - 1) / kChunk * kChunk;
                     const unsigned long long old = atomicAdd(
-                        reinterpret_cast<unsigned long long*>(list.counts), (1ull << 32) | n);
+                        reinterpret_cast<unsigned long long*>(list.counts), (1ull << 32) | padded);
+                    atomicAdd(&list.counts[4], n);
                     const uint32_t slot = static_cast<uint32_t>(old >> 32);
                     list.entries[slot] = (frame << 24) | static_cast<uint32_t>(ty * tiles_across(d) + tx);
                     list.ranks[slot] = static_cast<uint32_t>(old);
@@ -633,11 +693,9 @@ void fit_batch_f32(const FitDesc* frames, const uint32_t* first_tile, const uint
 }
 
 // ---------------------------------------------------------------------------- FP64 pass
-// Each listed pixel is fitted by a group of kRefitLanes lanes that split its window rows;
-// a wave takes 64 / kRefitLanes consecutive ranks at a time from counts[3], so the work is
-// shared out pixel by pixel whatever the tiles the pixels came from.
-constexpr int kRefitLanes = 4;
-constexpr uint32_t kRanksPerWave = 64 / kRefitLanes;
+// The FP64 pass takes kChunk consecutive ranks at a time per wave from counts[3]; as the
+// ranks of an entry are padded to whole chunks, a chunk holds up to kChunk listed pixels
+// of one tile, so the work is shared out chunk by chunk whatever the tiles' loads.
 
 // Position (0..63) of the n-th set bit (n counted from 0) of m; m has more than n bits.
 __device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
@@ -657,37 +715,74 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
     return pos;
 }
 
-// The listed pixel of rank q < listed pixels: its entry (the last whose rank is <= q)
-// and its thread within the entry's tile.
-__device__ __forceinline__ void listed_pixel(const RefitList& list, uint32_t entries, uint32_t q,
-                                             uint32_t& entry, int& thread) {
+// The entry holding rank q (q below counts[0]): the last entry whose first rank is <= q.
+__device__ __forceinline__ uint32_t entry_of(const RefitList& list, uint32_t entries, uint32_t q) {
     uint32_t lo = 0, hi = entries - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) / 2;
         if (list.ranks[mid] <= q) lo = mid; else hi = mid - 1;
     }
-    entry = list.entries[lo];
-    int n = static_cast<int>(q - list.ranks[lo]);
-    const uint64_t* m = list.masks + 4 * static_cast<size_t>(lo);
-    int w = 0;
-    for (; w < 3; ++w) {
-        const int c = __popcll(m[w]);
-        if (n < c) break;
-        n -= c;
-    }
-    thread = w * 64 + nth_set_bit(m[w], n);
+    return lo;
 }
 
-// The next kRanksPerWave ranks for this wave (the same value in every lane).
+// Thread (pixel of the tile) of the n-th listed pixel of an entry's 256-bit mask m, or -1
+// when the entry lists no more than n pixels.
+__device__ __forceinline__ int listed_thread(const uint64_t* m, int n) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int c = __popcll(m[w]);
+        if (n < c) return w * 64 + nth_set_bit(m[w], n);
+        n -= c;
+    }
+    return -1;
+}
+
+// The next kChunk ranks for this wave (the same value in every lane).
 __device__ __forceinline__ uint32_t next_ranks(uint32_t* counter) {
     uint32_t base = 0;
-    if ((threadIdx.x % 64) == 0) base = atomicAdd(counter, kRanksPerWave);
+    if ((threadIdx.x % 64) == 0) base = atomicAdd(counter, kChunk);
     return __builtin_amdgcn_readfirstlane(base);
 }
 
+// FP64 pass over the listed pixels of one frame; one wave per workgroup, persistent
+// (waves loop until the ranks run out).  For each chunk the wave stages its tile plus halo
+// in LDS, as the FP32 pass did, and fits the chunk's pixels from there.
 template <int R>
-__device__ __forceinline__ void refit_pixel(const FitDesc& d, uint32_t tile, int thread,
-                                            const LaneGroup<kRefitLanes>& grp) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
+void refit_f64(FitDesc d, RefitList list) {
+    extern __shared__ float2 region[];
+    const uint32_t ranks = list.counts[0], entries = list.counts[1];
+    const int tw = d.tile_w, th = 256 / tw;
+    const int halo = max(R, d.normal_radius);
+    const int pitch = tw + 2 * halo;
+    const int across = tiles_across(d);
+    const LaneGroup<kRefitLanes> grp{static_cast<int>(threadIdx.x % kRefitLanes)};
+    for (;;) {
+        const uint32_t base = next_ranks(&list.counts[3]);
+        if (base >= ranks) break;
+        const uint32_t slot = __builtin_amdgcn_readfirstlane(entry_of(list, entries, base));
+        const uint32_t tile = list.entries[slot] & 0xffffffu;
+        const int bx = static_cast<int>(tile % across) * tw, by = static_cast<int>(tile / across) * th;
+        stage_region(d, region, bx - halo, by - halo, pitch, th + 2 * halo);
+        const int t = listed_thread(list.masks + 4 * static_cast<size_t>(slot),
+                                    static_cast<int>(base - list.ranks[slot] + threadIdx.x / kRefitLanes));
+        if (t >= 0) {
+            const int lx = t % tw, ly = t / tw;
+            const float2* centre = region + (ly + halo) * pitch + (lx + halo);
+            const PixelFit<double> r = fit_pixel<double, R, kRefitLanes>(
+                d, LdsSource{centre, pitch}, bx + lx, by + ly, centre->x, d.residual != nullptr, grp);
+            if (grp.part == 0) store_pixel(d, static_cast<int64_t>(by + ly) * d.width + bx + lx, r);
+        }
+        __syncthreads();   // the next chunk re-stages the region
+    }
+}
+
+// FP64 pass over the listed pixels of a batch, reading the windows from the depth images.
+// Every chunk lies in one entry, hence one frame, so the frame's descriptor and window
+// radius are uniform across the wave.
+template <int R>
+__device__ __forceinline__ void refit_pixel_global(const FitDesc& d, uint32_t tile, int thread,
+                                                   const LaneGroup<kRefitLanes>& grp) {
     const int tw = d.tile_w, th = 256 / tw;
     const int across = tiles_across(d);
     const int u = static_cast<int>(tile % across) * tw + thread % tw;
@@ -699,54 +794,22 @@ __device__ __forceinline__ void refit_pixel(const FitDesc& d, uint32_t tile, int
     if (grp.part == 0) store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
 }
 
-// FP64 pass over the listed pixels of one frame (persistent: waves loop until the ranks
-// run out).
-template <int R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
-void refit_f64(FitDesc d, RefitList list) {
-    const uint32_t pixels = list.counts[0], entries = list.counts[1];
-    const int lane = threadIdx.x % 64;
-    const LaneGroup<kRefitLanes> grp{lane % kRefitLanes};
-    for (;;) {
-        const uint32_t base = next_ranks(&list.counts[3]);
-        if (base >= pixels) break;
-        const uint32_t q = base + static_cast<uint32_t>(lane / kRefitLanes);
-        if (q < pixels) {
-            uint32_t entry;
-            int thread;
-            listed_pixel(list, entries, q, entry, thread);
-            refit_pixel<R>(d, entry & 0xffffffu, thread, grp);
-        }
-    }
-}
-
-// FP64 pass over the listed pixels of a batch.  The ranks a wave takes may span frames;
-// the wave then handles one frame at a time, so that the frame's descriptor and window
-// radius stay uniform.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
 void refit_batch_f64(const FitDesc* frames, RefitList list) {
-    const uint32_t pixels = list.counts[0], entries = list.counts[1];
-    const int lane = threadIdx.x % 64;
-    const LaneGroup<kRefitLanes> grp{lane % kRefitLanes};
+    const uint32_t ranks = list.counts[0], entries = list.counts[1];
+    const LaneGroup<kRefitLanes> grp{static_cast<int>(threadIdx.x % kRefitLanes)};
     for (;;) {
         const uint32_t base = next_ranks(&list.counts[3]);
-        if (base >= pixels) break;
-        const uint32_t q = base + static_cast<uint32_t>(lane / kRefitLanes);
-        bool pending = q < pixels;
-        uint32_t entry = 0;
-        int thread = 0;
-        if (pending) listed_pixel(list, entries, q, entry, thread);
-        for (;;) {
-            const uint64_t waiting = __ballot(pending);
-            if (waiting == 0) break;
-            const uint32_t f = __builtin_amdgcn_readlane(entry >> 24, __ffsll(static_cast<long long>(waiting)) - 1);
-            if (pending && (entry >> 24) == f) {
-                const FitDesc d = frames[f];
-                with_radius(d.radius, [&](auto rc) {
-                    refit_pixel<decltype(rc)::value>(d, entry & 0xffffffu, thread, grp);
-                });
-                pending = false;
-            }
+        if (base >= ranks) break;
+        const uint32_t slot = __builtin_amdgcn_readfirstlane(entry_of(list, entries, base));
+        const uint32_t entry = __builtin_amdgcn_readfirstlane(list.entries[slot]);
+        const int t = listed_thread(list.masks + 4 * static_cast<size_t>(slot),
+                                    static_cast<int>(base - list.ranks[slot] + (threadIdx.x % 64) / kRefitLanes));
+        const FitDesc d = frames[entry >> 24];
+        if (t >= 0) {
+            with_radius(d.radius, [&](auto rc) {
+                refit_pixel_global<decltype(rc)::value>(d, entry & 0xffffffu, t, grp);
+            });
         }
     }
 }
@@ -756,7 +819,7 @@ size_t lds_bytes(int tile_w, int tile_h, int halo) {
 }
 
 template <int R>
-hipError_t launch_radius(const FitDesc& d, const RefitList& list, int workgroups, hipStream_t st,
+hipError_t launch_radius(const FitDesc& d, const RefitList& list, int cus, hipStream_t st,
                          hipEvent_t* ev) {
     const int halo = R > d.normal_radius ? R : d.normal_radius;
     hipError_t e;
@@ -778,7 +841,7 @@ hipError_t launch_radius(const FitDesc& d, const RefitList& list, int workgroups
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
     if (d.precision == 0) {
-        hipLaunchKernelGGL(refit_f64<R>, dim3(workgroups), dim3(256), 0, st, d, list);
+        hipLaunchKernelGGL(refit_f64<R>, dim3(16 * cus), dim3(64), lds, st, d, list);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
@@ -786,10 +849,10 @@ hipError_t launch_radius(const FitDesc& d, const RefitList& list, int workgroups
 }
 
 template <int... Rs>
-hipError_t dispatch_radius(int r, const FitDesc& d, const RefitList& list, int workgroups,
+hipError_t dispatch_radius(int r, const FitDesc& d, const RefitList& list, int cus,
                            hipStream_t st, hipEvent_t* ev, std::integer_sequence<int, Rs...>) {
     hipError_t e = hipErrorInvalidValue;
-    (void)((r == Rs + 1 ? (e = launch_radius<Rs + 1>(d, list, workgroups, st, ev), true) : false) || ...);
+    (void)((r == Rs + 1 ? (e = launch_radius<Rs + 1>(d, list, cus, st, ev), true) : false) || ...);
     return e;
 }
 
@@ -818,14 +881,14 @@ RefitList refit_list(void* storage, int64_t tiles, uint32_t* counts) {
     return l;
 }
 
-hipError_t launch_fit(const FitDesc& d, const RefitList& list, int workgroups, hipStream_t stream,
+hipError_t launch_fit(const FitDesc& d, const RefitList& list, int cus, hipStream_t stream,
                       hipEvent_t* events) {
     if (d.precision != 2) {
         hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, list.counts);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return dispatch_radius(d.radius, d, list, workgroups, stream, events,
+    return dispatch_radius(d.radius, d, list, cus, stream, events,
                            std::make_integer_sequence<int, kMaxRadius>{});
 }
 

@@ -49,7 +49,7 @@ struct qc_context {
     int cus = 0;
     int last_hip_error = 0;
     void* refit_storage = nullptr;     // device, refit list for `capacity` entries
-    uint32_t* refit_counts = nullptr;  // device, 4 counters
+    uint32_t* refit_counts = nullptr;  // device, kCountWords counters
     int64_t capacity = 0;
     hipStream_t last_stream = nullptr;
     int last_precision = 0;
@@ -194,7 +194,7 @@ qc_status prepare_slot(qc_context* ctx, BatchSlot& s, int64_t entries) {
         s.host = static_cast<BatchStaging*>(h);
         if ((e = hipMalloc(&dv, sizeof(BatchStaging))) != hipSuccess) return hip_fail(ctx, e);
         s.dev = static_cast<BatchStaging*>(dv);
-        if ((e = hipMalloc(&c, 4 * sizeof(uint32_t))) != hipSuccess) return hip_fail(ctx, e);
+        if ((e = hipMalloc(&c, qc::kCountWords * sizeof(uint32_t))) != hipSuccess) return hip_fail(ctx, e);
         s.counts = static_cast<uint32_t*>(c);
         if ((e = hipEventCreate(&s.done)) != hipSuccess) return hip_fail(ctx, e);
     }
@@ -268,7 +268,7 @@ qc_status qc_create(qc_context** out, int device) {
     void* p = nullptr;
     if ((e = hipSetDevice(device)) != hipSuccess ||
         (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess ||
-        (e = hipMalloc(&p, 4 * sizeof(uint32_t))) != hipSuccess ||
+        (e = hipMalloc(&p, qc::kCountWords * sizeof(uint32_t))) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
         if (p) (void)hipFree(p);
         delete ctx;
@@ -320,7 +320,7 @@ qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params
         ctx->pending.insert(ctx->pending.end(), ev, ev + 3);
     }
     const qc::RefitList list = qc::refit_list(ctx->refit_storage, ctx->capacity, ctx->refit_counts);
-    if ((e = qc::launch_fit(d, list, 4 * ctx->cus, s, ctx->timing ? ev : nullptr)) != hipSuccess)
+    if ((e = qc::launch_fit(d, list, ctx->cus, s, ctx->timing ? ev : nullptr)) != hipSuccess)
         return hip_fail(ctx, e);
     ctx->last_stream = s;
     ctx->last_precision = params->precision;
@@ -470,10 +470,10 @@ qc_status qc_last_refit_count(qc_context* ctx, uint32_t* count) {
     hipError_t e;
     if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
     if ((e = hipStreamSynchronize(ctx->last_stream)) != hipSuccess) return hip_fail(ctx, e);
-    uint32_t counts[2] = {0, 0};   // [0] listed pixels, [1] list entries
+    uint32_t counts[qc::kCountWords] = {};
     if ((e = hipMemcpy(counts, ctx->refit_counts, sizeof counts, hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(ctx, e);
-    *count = counts[0];
+    *count = counts[4];   // listed pixels
     return QC_OK;
 }
 
