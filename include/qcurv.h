@@ -75,7 +75,12 @@ typedef struct {
     int32_t normal_radius;   /* initial-normal window (2r_n+1)^2, 1..QC_MAX_RADIUS; 3 = 7x7 */
     int32_t iterations;      /* fixed number of re-weighted Gauss-Newton steps, 0..64 */
     float k;                 /* robust constant of Eq. (11), m^2, > 0 */
-    int32_t reject;          /* 0 only: the rejection variant of Eq. (11) is not built */
+    int32_t reject;          /* 0: weights k / (k + e^2) (Eq. (11)); 1: also reject (weight 0)
+                                every neighbour with e^2 >= R, R = 2 x the unweighted mean
+                                of e^2 over the window at the current parameters
+                                (Section 3.2.3; nothing rejected when that mean is 0).
+                                MIXED also recomputes in FP64 every pixel with an FP32
+                                decision within a relative 2e-5 of R. */
     float depth_scale;       /* metres per unit of U16 depth; ignored for F16/F32 */
     int32_t precision;       /* qc_precision */
     float cond_max;          /* MIXED: refit if the equilibrated pivot ratio exceeds this */
@@ -134,7 +139,8 @@ typedef struct {
  * persistent FP32 launch over all their tiles and one persistent FP64 recomputation
  * launch (MIXED), replayed from a HIP graph the context captures once.  Each item's
  * outputs equal, bit for bit, those of qc_fit on the same item.  All items must use the
- * same precision, MIXED or FP32 (FP64 frames go through qc_fit).  At most two batches
+ * same precision, MIXED or FP32 (FP64 frames go through qc_fit).  A batch holding an item
+ * with reject = 1 runs as per-frame launches in item order instead.  At most two batches
  * are in flight per context; a third call first waits for the oldest.  Asynchronous on
  * `stream`; the items array itself may be reused as soon as the call returns. */
 qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, void* stream);

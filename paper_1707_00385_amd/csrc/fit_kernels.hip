@@ -34,6 +34,9 @@ namespace {
 constexpr int kMaxRadius = 18;
 constexpr uint8_t kFlagValid = 1, kFlagFp64 = 2, kFlagIll = 4;
 constexpr int kTileW = 16;
+// Relative distance from the rejection bound R within which an FP32 decision e^2 < R is
+// not trusted (about 10x the FP32 error of e^2 for residuals at the noise level).
+constexpr float kRejectMargin = 2e-5f;
 
 #ifndef QC_F32_WAVES_PER_EU
 #define QC_F32_WAVES_PER_EU 4
@@ -223,7 +226,7 @@ __device__ __forceinline__ void for_window(const Src& src, int radius, const Lan
 
 // The pixel's fit, Section 3.2: initial normal (Eq. (7)), frame set-up, fixed number of
 // re-weighted Gauss-Newton steps (Eqs. (8)-(11)), curvatures, refined normal.
-template <typename Real, int RC, int NP = 1, typename Src>
+template <typename Real, int RC, int NP = 1, bool REJ = false, typename Src>
 __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int v, float Dc_f,
                                     bool want_residual, LaneGroup<NP> grp = LaneGroup<NP>{0}) {
     PixelFit<Real> out;
@@ -320,6 +323,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
     }
     Real tz = 0, A = 0, B = 0, C = 0;     // patch coefficients in units of h
     Acc kappa_max = 0, last_step = 0;
+    bool near = false;                    // an FP32 rejection decision was too close to call
     // window half-extent r Z_c / fx in units of h
     const Acc hwin = Acc(radius) * Acc(g.Dc) * Acc(s) / Acc(fx) * Acc(g.ih);
 
@@ -335,6 +339,26 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             Rp[i][2] = f * fmaT(R[i][0], g.g02, fmaT(R[i][1], g.g12, R[i][2] * g.g22));
         }
         const Real Ah = Real(0.5) * A, Bh = Real(0.5) * B, Ch = Real(0.5) * C;
+        // Rejection (Eq. (11) with R = 2 MSE, Section 3.2.3): R from the unweighted mean
+        // of e^2 over the valid neighbours at the current parameters; none when it is 0.
+        Real thresh = Real(INFINITY);
+        if constexpr (REJ) {
+            Acc se = 0;
+            for_window<RC, sizeof(Real) == 8 ? QC_F64_UNROLL : 0>(src, radius, grp, [&](float2 t, int du, int dv) {
+                const Real D = Real(t.x), dD = D - g.Dc;
+                const Real fdu = Real(du), fdv = Real(dv);
+                const Real sx = fmaT(fmaT(Rp[0][0], fdu, Rp[0][1] * fdv), D, Rp[0][2] * dD);
+                const Real sy = fmaT(fmaT(Rp[1][0], fdu, Rp[1][1] * fdv), D, Rp[1][2] * dD);
+                const Real sz2 = fmaT(fmaT(Rp[2][0], fdu, Rp[2][1] * fdv), D, Rp[2][2] * dD);
+                const Real qz = fmaT(Real(0.5), sz2, tz);
+                const Real ap = fmaT(Ah, sx, Bh * sy), cp = fmaT(Bh, sx, Ch * sy);
+                const Real e = fmaT(ap, sx, fmaT(cp, sy, -qz));
+                se += present(t) ? Acc(e * e) : Acc(0);
+            });
+            se = grp.sum(se);
+            const Acc mse = se / Acc(nfit);
+            if (mse > Acc(0)) thresh = Real(Acc(2) * mse);
+        }
         // accumulators: Hij = sum ji jj with j = sqrt(w) * (J0, J1, -1, sx^2, sx sy, sy^2);
         // S_i = sum ji sqrt(w) (column 2 up to sign); Gi = sum ji sqrt(w) e.
         // The sums are accumulated in FP64 whatever the per-neighbour precision: FP32
@@ -355,7 +379,14 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             const Real ap = fmaT(Ah, sx, Bh * sy);          // (A qx + B qy) / 2
             const Real cp = fmaT(Bh, sx, Ch * sy);          // (B qx + C qy) / 2
             const Real e = fmaT(ap, sx, fmaT(cp, sy, -qz)); // Eq. (6): A/2 qx^2 + B qx qy + C/2 qy^2 - qz
-            const Real rw = rsqrtT(fmaT(e, e, Real(t.y)));  // sqrt of the weight, Eq. (11)
+            Real c = Real(t.y);
+            if constexpr (REJ) {
+                const Real e2 = e * e;
+                // an FP32 decision too close to R to be sure of is left to FP64
+                if (fp32 && present(t) && fabs(e2 - thresh) <= Real(kRejectMargin) * thresh) near = true;
+                c = e2 < thresh ? c : Real(INFINITY);
+            }
+            const Real rw = rsqrtT(fmaT(e, e, c));          // sqrt of the weight, Eq. (11)
             const Real J0 = -fmaT(cp, sz2, sy);             // de/dtheta_x
             const Real J1 = fmaT(ap, sz2, sx);              // de/dtheta_y
             const Real j0r = rw * J0, j1r = rw * J1;
@@ -495,6 +526,24 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             Rp[i][2] = fmaT(R[i][0], g.g02, fmaT(R[i][1], g.g12, R[i][2] * g.g22));
         }
         const Real Ah = Real(0.5) * A, Bh = Real(0.5) * B, Ch = Real(0.5) * C;
+        Real thresh = Real(INFINITY);
+        if constexpr (REJ) {
+            Acc se = 0;
+            for_window<RC, sizeof(Real) == 8 ? QC_F64_UNROLL : 0>(src, radius, grp, [&](float2 t, int du, int dv) {
+                const Real D = Real(t.x), dD = D - g.Dc;
+                const Real mx = Real(du) * D, my = Real(dv) * D;
+                const Real sx = fmaT(Rp[0][0], mx, fmaT(Rp[0][1], my, Rp[0][2] * dD));
+                const Real sy = fmaT(Rp[1][0], mx, fmaT(Rp[1][1], my, Rp[1][2] * dD));
+                const Real sz = fmaT(Rp[2][0], mx, fmaT(Rp[2][1], my, Rp[2][2] * dD));
+                const Real qz = sz + tz;
+                const Real ap = fmaT(Ah, sx, Bh * sy), cp = fmaT(Bh, sx, Ch * sy);
+                const Real e = fmaT(ap, sx, fmaT(cp, sy, -qz));
+                se += present(t) ? Acc(e * e) : Acc(0);
+            });
+            se = grp.sum(se);
+            const Acc mse = se / Acc(nfit);
+            if (mse > Acc(0)) thresh = Real(Acc(2) * mse);
+        }
         Real sw = 0, swe = 0;
         for_window<RC, sizeof(Real) == 8 ? QC_F64_UNROLL : 0>(src, radius, grp, [&](float2 t, int du, int dv) {
             const Real D = Real(t.x), dD = D - g.Dc;
@@ -505,7 +554,13 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             const Real qz = sz + tz;
             const Real ap = fmaT(Ah, sx, Bh * sy), cp = fmaT(Bh, sx, Ch * sy);
             const Real e = fmaT(ap, sx, fmaT(cp, sy, -qz));
-            const Real rw = rsqrtT(fmaT(e, e, Real(t.y)));
+            Real c = Real(t.y);
+            if constexpr (REJ) {
+                const Real e2 = e * e;
+                if (fp32 && present(t) && fabs(e2 - thresh) <= Real(kRejectMargin) * thresh) near = true;
+                c = e2 < thresh ? c : Real(INFINITY);
+            }
+            const Real rw = rsqrtT(fmaT(e, e, c));
             const Real w = rw * rw;
             sw += w;
             swe = fmaT(w * e, e, swe);
@@ -526,7 +581,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
     out.n[1] = R[2][1];
     out.n[2] = R[2][2];
     out.flags = kFlagValid | (fp32 ? 0 : kFlagFp64);
-    if (fp32 && (ill || !(kappa_max <= Acc(d.cond_max)) || !(last_step <= Acc(d.step_max))))
+    if (fp32 && (ill || near || !(kappa_max <= Acc(d.cond_max)) || !(last_step <= Acc(d.step_max))))
         out.flags |= kFlagIll;
     return out;
 }
@@ -582,7 +637,7 @@ __device__ __forceinline__ int tiles_across(const FitDesc& d) {
 // MIXED precision the pixels whose FP32 fit is unreliable are not stored but listed: one
 // list entry for the tile with a 256-bit mask of them (bit t = thread t = pixel
 // (t % tw, t / tw)) and the rank of its first listed pixel.
-template <typename Real, int R>
+template <typename Real, int R, bool REJ = false>
 __device__ __forceinline__ void fit_tile_body(const FitDesc& d, int tx, int ty, uint32_t frame,
                                               const RefitList& list) {
     extern __shared__ float2 tile[];
@@ -599,7 +654,7 @@ __device__ __forceinline__ void fit_tile_body(const FitDesc& d, int tx, int ty, 
         const float2* centre = tile + (ly + halo) * pitch + (lx + halo);
         const PixelFit<Real> r = !present(*centre)
             ? missing_pixel<Real>()
-            : fit_pixel<Real, R>(d, LdsSource{centre, pitch}, u, v, centre->x, d.residual != nullptr);
+            : fit_pixel<Real, R, 1, REJ>(d, LdsSource{centre, pitch}, u, v, centre->x, d.residual != nullptr);
         recompute = mixed && (r.flags & kFlagIll) != 0;
         if (!recompute) store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
     }
@@ -645,18 +700,19 @@ __device__ __forceinline__ void with_radius(int r, F&& f) {
     with_radius(r, f, std::make_integer_sequence<int, kMaxRadius>{});
 }
 
-// FP32 pass over one frame: one 256-lane workgroup per tile.
-template <int R>
+// FP32 pass over one frame: one 256-lane workgroup per tile.  REJ: the rejection variant
+// of Eq. (11).
+template <int R, bool REJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))
 void fit_tile_f32(FitDesc d, RefitList list) {
-    fit_tile_body<float, R>(d, blockIdx.x, blockIdx.y, 0u, list);
+    fit_tile_body<float, R, REJ>(d, blockIdx.x, blockIdx.y, 0u, list);
 }
 
 // FP64 pass over every pixel of one frame: 16x4 tiles.
-template <int R>
+template <int R, bool REJ>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
 void fit_tile_f64(FitDesc d, RefitList list) {
-    fit_tile_body<double, R>(d, blockIdx.x, blockIdx.y, 0u, list);
+    fit_tile_body<double, R, REJ>(d, blockIdx.x, blockIdx.y, 0u, list);
 }
 
 // Persistent FP32 pass over a batch of frames.  Tiles are numbered frame after frame
@@ -747,7 +803,7 @@ __device__ __forceinline__ uint32_t next_ranks(uint32_t* counter) {
 // FP64 pass over the listed pixels of one frame; one wave per workgroup, persistent
 // (waves loop until the ranks run out).  For each chunk the wave stages its tile plus halo
 // in LDS, as the FP32 pass did, and fits the chunk's pixels from there.
-template <int R>
+template <int R, bool REJ>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
 void refit_f64(FitDesc d, RefitList list) {
     extern __shared__ float2 region[];
@@ -769,7 +825,7 @@ void refit_f64(FitDesc d, RefitList list) {
         if (t >= 0) {
             const int lx = t % tw, ly = t / tw;
             const float2* centre = region + (ly + halo) * pitch + (lx + halo);
-            const PixelFit<double> r = fit_pixel<double, R, kRefitLanes>(
+            const PixelFit<double> r = fit_pixel<double, R, kRefitLanes, REJ>(
                 d, LdsSource{centre, pitch}, bx + lx, by + ly, centre->x, d.residual != nullptr, grp);
             if (grp.part == 0) store_pixel(d, static_cast<int64_t>(by + ly) * d.width + bx + lx, r);
         }
@@ -818,9 +874,9 @@ size_t lds_bytes(int tile_w, int tile_h, int halo) {
     return sizeof(float2) * static_cast<size_t>(tile_w + 2 * halo) * static_cast<size_t>(tile_h + 2 * halo);
 }
 
-template <int R>
-hipError_t launch_radius(const FitDesc& d, const RefitList& list, int cus, hipStream_t st,
-                         hipEvent_t* ev) {
+template <int R, bool REJ>
+hipError_t launch_variant(const FitDesc& d, const RefitList& list, int cus, hipStream_t st,
+                          hipEvent_t* ev) {
     const int halo = R > d.normal_radius ? R : d.normal_radius;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
@@ -828,7 +884,7 @@ hipError_t launch_radius(const FitDesc& d, const RefitList& list, int cus, hipSt
         FitDesc d64 = d;
         d64.tile_w = kTileW;
         dim3 grid((d.width + kTileW - 1) / kTileW, (d.height + 3) / 4);
-        hipLaunchKernelGGL(fit_tile_f64<R>, grid, dim3(64), lds_bytes(kTileW, 4, halo), st, d64, list);
+        hipLaunchKernelGGL((fit_tile_f64<R, REJ>), grid, dim3(64), lds_bytes(kTileW, 4, halo), st, d64, list);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
@@ -837,15 +893,22 @@ hipError_t launch_radius(const FitDesc& d, const RefitList& list, int cus, hipSt
     const int tw = d.tile_w, th = 256 / tw;
     const size_t lds = lds_bytes(tw, th, halo);
     dim3 grid((d.width + tw - 1) / tw, (d.height + th - 1) / th);
-    hipLaunchKernelGGL(fit_tile_f32<R>, grid, dim3(256), lds, st, d, list);
+    hipLaunchKernelGGL((fit_tile_f32<R, REJ>), grid, dim3(256), lds, st, d, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
     if (d.precision == 0) {
-        hipLaunchKernelGGL(refit_f64<R>, dim3(16 * cus), dim3(64), lds, st, d, list);
+        hipLaunchKernelGGL((refit_f64<R, REJ>), dim3(16 * cus), dim3(64), lds, st, d, list);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
     return hipSuccess;
+}
+
+template <int R>
+hipError_t launch_radius(const FitDesc& d, const RefitList& list, int cus, hipStream_t st,
+                         hipEvent_t* ev) {
+    return d.reject ? launch_variant<R, true>(d, list, cus, st, ev)
+                    : launch_variant<R, false>(d, list, cus, st, ev);
 }
 
 template <int... Rs>

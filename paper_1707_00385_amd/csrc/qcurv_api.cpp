@@ -91,7 +91,7 @@ qc_status check_params(const qc_params* p) {
     if (p->precision < QC_PREC_MIXED || p->precision > QC_PREC_FP64) return QC_ERR_INVALID_ARG;
     if (std::isnan(p->cond_max) || std::isnan(p->step_max)) return QC_ERR_INVALID_ARG;
     if (p->tile_width != 0 && !qc::valid_tile_width(p->tile_width)) return QC_ERR_INVALID_ARG;
-    if (p->reject != 0) return QC_ERR_UNSUPPORTED;
+    if (p->reject != 0 && p->reject != 1) return QC_ERR_INVALID_ARG;
     return QC_OK;
 }
 
@@ -144,6 +144,7 @@ qc::FitDesc make_desc(const qc_frame* frame, const qc_params* params, const qc_o
     d.cond_max = params->cond_max;
     d.step_max = params->step_max;
     d.precision = params->precision;
+    d.reject = params->reject;
     d.tile_w = tile_w;
     d.k1 = out->k1;
     d.k2 = out->k2;
@@ -332,12 +333,14 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
     if (n == 0) return QC_OK;
     qc_status st;
     const int32_t prec = items[0].params.precision;
+    bool any_reject = false;
     for (int32_t i = 0; i < n; ++i) {
         const qc_batch_item& it = items[i];
         if ((st = check_frame(&it.frame)) != QC_OK) return st;
         if ((st = check_params(&it.params)) != QC_OK) return st;
         if (!it.out.k1 || !it.out.k2) return QC_ERR_INVALID_ARG;
         if (it.params.precision != prec) return QC_ERR_INVALID_ARG;
+        any_reject |= it.params.reject != 0;
     }
     if (prec == QC_PREC_FP64) return QC_ERR_UNSUPPORTED;
     hipError_t e;
@@ -372,7 +375,14 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
     std::memcpy(s.host->first_tile, first.data(), sizeof(uint32_t) * (n + 1));
     s.host->header[0] = static_cast<uint32_t>(n);
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    if (ctx->timing) {
+    if (any_reject) {
+        // The batched kernels carry only the default weights of Eq. (11): a batch holding
+        // rejection frames runs as per-frame launches, in order on the stream, on the
+        // slot's own list (so that two batches in flight on two streams share none).
+        const qc::RefitList list = qc::refit_list(s.list, s.capacity, s.counts);
+        for (int32_t j = 0; j < n; ++j)
+            if ((e = qc::launch_fit(descs[j], list, ctx->cus, hs)) != hipSuccess) return hip_fail(ctx, e);
+    } else if (ctx->timing) {
         // timed batches run eagerly so that the two passes can be bracketed separately
         hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
         for (auto& x : ev)

@@ -98,6 +98,21 @@ def test_batch_equals_per_frame_calls(ctx):
         _equal({k: v.cpu().numpy() for k, v in o.items()}, single, f"frame {i}")
 
 
+def test_batch_with_rejection_equals_per_frame_calls(ctx):
+    """Batches holding rejection-variant items run as per-frame launches: same outputs."""
+    import torch
+    jobs = _jobs()[:4]
+    bj = _batch_jobs(jobs)
+    for i, (_, _, p, _) in enumerate(bj):
+        p.reject = i % 2
+    log(f"[case] batch of {len(bj)} frames, alternate items with rejection")
+    outs = ctx.fit_batch(bj)
+    torch.cuda.synchronize()
+    for i, ((t, K, p, _), o) in enumerate(zip(bj, outs)):
+        single = _run_single(ctx, t, jobs[i][1], p)
+        _equal({k: v.cpu().numpy() for k, v in o.items()}, single, f"frame {i}")
+
+
 def test_batch_graph_replays_match_eager(ctx):
     """The batch runs from a captured graph; replay it several times with the program's
     own GPU work and synchronisations in between, and check every replay."""

@@ -26,11 +26,13 @@ def ctx():
 
 
 def _run(ctx, name, depth, fmt, cam, radius, iterations, tol, precision="mixed", k=1e-5,
-         normal_radius=3, **kw):
-    log(f"[case] {name} fmt={fmt} {cam.width}x{cam.height} r={radius} T={iterations} {precision}")
+         normal_radius=3, reject=False, **kw):
+    log(f"[case] {name} fmt={fmt} {cam.width}x{cam.height} r={radius} T={iterations} {precision}"
+        f"{' reject' if reject else ''}")
     g = gpu_fit(ctx, depth, fmt, cam, radius=radius, iterations=iterations, k=k,
-                normal_radius=normal_radius, precision=precision)
-    o, oa = oracle_pair(depth, fmt, cam, radius, iterations, k, normal_radius=normal_radius)
+                normal_radius=normal_radius, precision=precision, reject=int(reject))
+    o, oa = oracle_pair(depth, fmt, cam, radius, iterations, k, normal_radius=normal_radius,
+                        reject=reject)
     return compare(g, o, tol, name, o_alt=oa, **kw), g, o
 
 
@@ -95,3 +97,43 @@ def test_deterministic_repeat(ctx):
     b = gpu_fit(ctx, sc.depth_u16(), "u16", sc.camera, radius=4, iterations=5)
     for key in ("k1", "k2", "normal", "residual", "flags"):
         assert np.array_equal(a[key], b[key], equal_nan=True), key
+
+
+# ---- rejection variant ("Ours+R": Eq. (11) with R = 2 MSE, Section 3.2.3) ----
+# The decisions e^2 < R are discrete: a pixel whose oracle result moves under the
+# rounding-level probe (a decision at the bound) counts as non-unique like any other.
+# MIXED recomputes in FP64 every pixel with an FP32 decision near the bound.
+
+@pytest.mark.parametrize("fmt", ["u16", "f32"])
+def test_reject_clutter_small(ctx, fmt):
+    cam = scenes.Camera(100, 75, 90.0, 90.0, 49.5, 37.0)
+    sc = scenes.cluttered_scene(cam, seed_frame=11, config_index=8)
+    depth = sc.depth_u16() if fmt == "u16" else sc.depth_m
+    st, g, _ = _run(ctx, f"reject clutter100x75 {fmt}", depth, fmt, cam, 5, 5, 1e-3, reject=True,
+                    residual_tol=1e-2)
+    log("  refit fraction", st["refits"] / st["pixels"])
+
+
+def test_reject_vga_headline(ctx):
+    sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=2, config_index=1)
+    st, g, _ = _run(ctx, "reject vga u16", sc.depth_u16(), "u16", sc.camera, 7, 5, 1e-3, reject=True)
+    log("  refit fraction", st["refits"] / st["pixels"])
+
+
+def test_reject_fp64_mode_tight(ctx):
+    sc = scenes.cluttered_scene(scenes.Camera(96, 72, 80.0, 80.0, 47.5, 35.5), seed_frame=12,
+                                config_index=7)
+    _run(ctx, "reject fp64", sc.depth_u16(), "u16", sc.camera, 5, 5, 2e-7, precision="fp64",
+         reject=True, normal_tol=2e-7, residual_tol=2e-7)
+
+
+def test_reject_changes_results_near_outliers(ctx):
+    """The variant is not a no-op: on a noisy scene some fits change, and on pixels far
+    from depth edges the two variants stay close (both estimate the same surface)."""
+    cam = scenes.Camera(100, 75, 90.0, 90.0, 49.5, 37.0)
+    sc = scenes.cluttered_scene(cam, seed_frame=13, config_index=8)
+    a = gpu_fit(ctx, sc.depth_u16(), "u16", cam, radius=5, iterations=5, reject=0)
+    b = gpu_fit(ctx, sc.depth_u16(), "u16", cam, radius=5, iterations=5, reject=1)
+    both = ((a["flags"] & 1) == 1) & ((b["flags"] & 1) == 1)
+    diff = np.abs(a["k1"] - b["k1"])[both]
+    assert (diff > 0).mean() > 0.5
