@@ -30,7 +30,7 @@ N_FRAMES = 8                 # distinct seeded frames cycled through the timed s
 FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32 peak (256 CU x 2.4 GHz x 256 flop/clk)
 PROFILE_JSON = os.path.join(ROOT, "profiles", "fit_tile_f32_r7_vga_u16_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1707_00385_amd", "csrc", f)
-                  for f in ("fit_kernels.hip", "fit_internal.h")]
+                  for f in ("fit_device.h", "fit_frame.h", "fit_frame.hip", "fit_internal.h")]
 
 
 def kernel_source_hash() -> str:
@@ -239,6 +239,39 @@ def measure_batched(ctx, reps: int = 5) -> dict:
                    "Kinect-like u16; r in {3,5,7,11}, T in {3,5}, seeded"}
 
 
+def measure_rejection(ctx, dev, K, precision: str, steps: int = 100) -> dict:
+    """The rejection variant ("Ours+R": Eq. (11) with R = 2 MSE) on the headline frames:
+    per-frame fits as in the headline measurement, plus its FP64 recomputation share."""
+    import torch
+    from paper_1707_00385_amd.api import make_outputs, make_params
+    params = make_params(radius=RADIUS, iterations=ITERS, k=K_ROBUST, normal_radius=NRAD,
+                         precision=precision, reject=1)
+    out = make_outputs(HEIGHT, WIDTH, dev[0].device, flags=False)
+    for i in range(10):
+        ctx.fit(dev[i % N_FRAMES], K, params=params, out=out)
+    torch.cuda.synchronize()
+    ctx.get_timing(reset=True)
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ctx.fit(dev[i % N_FRAMES], K, params=params, out=out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.set_timing(False)
+    timing = ctx.get_timing(reset=True)
+    refits = []
+    for i in range(N_FRAMES):
+        ctx.fit(dev[i], K, params=params, out=out)
+        refits.append(ctx.last_refit_count())
+    calls = max(timing["calls"], 1)
+    return {"ms_per_frame": round(1e3 * wall / steps, 4),
+            "pixels_per_s": round(steps * WIDTH * HEIGHT / wall, 1),
+            "kernels_ms": {"fit_fp32": round(timing["fit_ms"] / calls, 4),
+                           "refit_fp64": round(timing["refit_ms"] / calls, 4)},
+            "refit_fraction": round(float(np.mean(refits)) / (WIDTH * HEIGHT), 5),
+            "workload": "headline frames, reject=1 (R = 2 x unweighted MSE of the window)"}
+
+
 def copy_calibration(nbytes: int) -> int:
     """Ten device-to-device copies of a known size: the HBM read/write counters of these
     dispatches give the scale factor between counter readings and bytes moved."""
@@ -262,6 +295,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-reject", action="store_true")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 10 plain device copies of BYTES bytes (calibrates the "
@@ -360,6 +394,8 @@ def main() -> int:
         "refit_fraction": round(float(np.mean(refits)) / (WIDTH * HEIGHT), 5),
         "roofline": roofline,
     }
+    if not args.no_reject:
+        result["rejection_variant"] = measure_rejection(ctx, dev, K, args.precision)
     if not args.no_batched and args.precision != "fp64":
         result["batched_form"] = measure_batched(ctx)
     if not args.no_served and args.precision != "fp64":

@@ -1,6 +1,7 @@
 """Builds libqcurv.so (HIP kernels for gfx950 + the C ABI) in-tree with hipcc."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -12,7 +13,9 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libqcurv.so")
 
-SOURCES = ["fit_kernels.hip", "qcurv_api.cpp", "serve.cpp"]
+# Kernel translation units (compiled in parallel: the per-frame kernels with and without
+# rejection and the batched kernels each instantiate every window radius) and the host side.
+SOURCES = ["fit_frame.hip", "fit_frame_reject.hip", "fit_batch.hip", "qcurv_api.cpp", "serve.cpp"]
 
 # Packed FP32 instructions are disabled: the compiler would otherwise form them from
 # scalar float code.  fp-contract is off so that every fused multiply-add is the one
@@ -30,18 +33,23 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False, extra: list | None = None) -> str:
-    objs = []
     build_dir = os.path.join(PKG, "_build")
     os.makedirs(build_dir, exist_ok=True)
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [hipcc()] + HIP_FLAGS + (extra or []) + ["-I", INCLUDE, "-I", CSRC] + lang + \
-              ["-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append([hipcc()] + HIP_FLAGS + (extra or []) + ["-I", INCLUDE, "-I", CSRC] +
+                    ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        procs = list(pool.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds))
+    for cmd, proc in zip(cmds, procs):
+        if verbose or proc.returncode != 0:
+            print(" ".join(cmd), flush=True)
+            sys.stderr.write(proc.stderr)
+        if proc.returncode != 0:
+            raise subprocess.CalledProcessError(proc.returncode, cmd)
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -1,0 +1,91 @@
+// fit_batch.hip -- the batched form: one persistent FP32 pass over the tiles of many
+// frames and one persistent FP64 pass over their listed pixels.
+#include "fit_device.h"
+
+namespace qc {
+namespace {
+
+// Persistent FP32 pass over a batch of frames.  Tiles are numbered frame after frame
+// (frames ordered by the host from most to least work per tile; first_tile[f] is the
+// number of the frame's first tile, first_tile[n] the total); every workgroup takes the
+// next tile number from counts[2] until none is left, so all frames share one launch.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))
+void fit_batch_f32(const FitDesc* frames, const uint32_t* first_tile, const uint32_t* header,
+                   RefitList list) {
+    __shared__ uint32_t next;
+    const uint32_t nf = header[0];
+    if (nf == 0) return;
+    const uint32_t total = first_tile[nf];
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(&list.counts[2], 1u);
+        __syncthreads();
+        const uint32_t t = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();
+        if (t >= total) break;
+        uint32_t lo = 0, hi = nf - 1;   // the frame holding tile t
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) / 2;
+            if (first_tile[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        const FitDesc d = frames[lo];
+        const int local = static_cast<int>(t - first_tile[lo]);
+        const int across = tiles_across(d);
+        with_radius(d.radius, [&](auto rc) {
+            fit_tile_body<float, decltype(rc)::value>(d, local % across, local / across, lo, list);
+        });
+        __syncthreads();   // the next tile re-stages LDS
+    }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
+void refit_batch_f64(const FitDesc* frames, RefitList list) {
+    const uint32_t ranks = list.counts[0], entries = list.counts[1];
+    const LaneGroup<kRefitLanes> grp{static_cast<int>(threadIdx.x % kRefitLanes)};
+    for (;;) {
+        const uint32_t base = next_ranks(&list.counts[3]);
+        if (base >= ranks) break;
+        const uint32_t slot = __builtin_amdgcn_readfirstlane(entry_of(list, entries, base));
+        const uint32_t entry = __builtin_amdgcn_readfirstlane(list.entries[slot]);
+        const int t = listed_thread(list.masks + 4 * static_cast<size_t>(slot),
+                                    static_cast<int>(base - list.ranks[slot] + (threadIdx.x % 64) / kRefitLanes));
+        const FitDesc d = frames[entry >> 24];
+        if (t >= 0) {
+            with_radius(d.radius, [&](auto rc) {
+                refit_pixel_global<decltype(rc)::value>(d, entry & 0xffffffu, t, grp);
+            });
+        }
+    }
+}
+
+}  // namespace
+
+size_t batch_lds_bytes() {
+    // largest staging region over the supported tile shapes at the largest halo
+    size_t m = 0;
+    for (int tw = 8; tw <= 64; tw *= 2) {
+        const size_t b = lds_bytes(tw, 256 / tw, kMaxRadius);
+        m = b > m ? b : m;
+    }
+    return m;
+}
+
+hipError_t launch_fit_batch(const FitDesc* frames, const uint32_t* first_tile,
+                            const uint32_t* header, int workgroups, const RefitList& list,
+                            hipStream_t stream, hipEvent_t* events) {
+    hipError_t e;
+    hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, list.counts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t lds = batch_lds_bytes();
+    if (events && (e = hipEventRecord(events[0], stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(fit_batch_f32, dim3(workgroups), dim3(256), lds, stream, frames, first_tile,
+                       header, list);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (events && (e = hipEventRecord(events[1], stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(refit_batch_f64, dim3(workgroups), dim3(256), 0, stream, frames, list);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (events && (e = hipEventRecord(events[2], stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+}  // namespace qc

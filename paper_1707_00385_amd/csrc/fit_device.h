@@ -1,4 +1,4 @@
-// fit_kernels.hip -- gfx950 kernels for per-pixel robust quadric-patch curvature fitting
+// fit_device.h -- device code shared by the gfx950 kernels for per-pixel robust quadric-patch curvature fitting
 // (Spek, Li, Drummond, "A Fast Method For Computing Principal Curvatures From Range
 // Images", Section 3).
 //
@@ -19,6 +19,8 @@
 //    Eq. (11) cancels in (J^T W J)^{-1} J^T W e.
 //  * The 6x6 solve is Jacobi-equilibrated LDL^T; the pivot ratio estimates the
 //    condition number that decides the FP64 recomputation.
+#pragma once
+
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -197,13 +199,17 @@ __device__ __forceinline__ void for_window(const Src& src, int radius, const Lan
                                            F&& f) {
     const int r = RC > 0 ? RC : radius;
     const int first = NP > 1 ? -r + grp.part : -r;
+    // The row loop stays rolled: unrolled, a short body (e.g. the mean of e^2 ahead of the
+    // accumulation) would keep a whole window of samples live across the two passes.
     if constexpr (RC > 0 && U == 0) {
+#pragma unroll 1
         for (int dv = first; dv <= r; dv += NP) {
             auto row = src.row(dv);
 #pragma unroll
             for (int du = -RC; du <= RC; ++du) f(row[du], du, dv);
         }
     } else if constexpr (U >= 2) {
+#pragma unroll 1
         for (int dv = first; dv <= r; dv += NP) {
             auto row = src.row(dv);
 #pragma unroll U
@@ -359,6 +365,9 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             const Acc mse = se / Acc(nfit);
             if (mse > Acc(0)) thresh = Real(Acc(2) * mse);
         }
+        // FP32: the closest any decision e^2 < R came to the bound; a pixel with one too
+        // close to be sure of is left to FP64
+        Real gap = Real(INFINITY);
         // accumulators: Hij = sum ji jj with j = sqrt(w) * (J0, J1, -1, sx^2, sx sy, sy^2);
         // S_i = sum ji sqrt(w) (column 2 up to sign); Gi = sum ji sqrt(w) e.
         // The sums are accumulated in FP64 whatever the per-neighbour precision: FP32
@@ -382,8 +391,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             Real c = Real(t.y);
             if constexpr (REJ) {
                 const Real e2 = e * e;
-                // an FP32 decision too close to R to be sure of is left to FP64
-                if (fp32 && present(t) && fabs(e2 - thresh) <= Real(kRejectMargin) * thresh) near = true;
+                if constexpr (sizeof(Real) == 4) gap = fmin(gap, present(t) ? fabs(e2 - thresh) : Real(INFINITY));
                 c = e2 < thresh ? c : Real(INFINITY);
             }
             const Real rw = rsqrtT(fmaT(e, e, c));          // sqrt of the weight, Eq. (11)
@@ -405,6 +413,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             G0 = fmaT(j0, je, G0); G1 = fmaT(j1, je, G1); G2 = fmaT(wr, je, G2);
             G3 = fmaT(j3, je, G3); G4 = fmaT(j4, je, G4); G5 = fmaT(j5, je, G5);
         });
+        if constexpr (REJ && sizeof(Real) == 4) near |= thresh < Real(INFINITY) && gap <= Real(kRejectMargin) * thresh;
         if constexpr (NP > 1) {
             H00 = grp.sum(H00); H01 = grp.sum(H01); H03 = grp.sum(H03); H04 = grp.sum(H04);
             H05 = grp.sum(H05); H11 = grp.sum(H11); H13 = grp.sum(H13); H14 = grp.sum(H14);
@@ -544,7 +553,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             const Acc mse = se / Acc(nfit);
             if (mse > Acc(0)) thresh = Real(Acc(2) * mse);
         }
-        Real sw = 0, swe = 0;
+        Real sw = 0, swe = 0, gap = Real(INFINITY);
         for_window<RC, sizeof(Real) == 8 ? QC_F64_UNROLL : 0>(src, radius, grp, [&](float2 t, int du, int dv) {
             const Real D = Real(t.x), dD = D - g.Dc;
             const Real mx = Real(du) * D, my = Real(dv) * D;
@@ -557,7 +566,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             Real c = Real(t.y);
             if constexpr (REJ) {
                 const Real e2 = e * e;
-                if (fp32 && present(t) && fabs(e2 - thresh) <= Real(kRejectMargin) * thresh) near = true;
+                if constexpr (sizeof(Real) == 4) gap = fmin(gap, present(t) ? fabs(e2 - thresh) : Real(INFINITY));
                 c = e2 < thresh ? c : Real(INFINITY);
             }
             const Real rw = rsqrtT(fmaT(e, e, c));
@@ -565,6 +574,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             sw += w;
             swe = fmaT(w * e, e, swe);
         });
+        if constexpr (REJ && sizeof(Real) == 4) near |= thresh < Real(INFINITY) && gap <= Real(kRejectMargin) * thresh;
         sw = grp.sum(sw);
         swe = grp.sum(swe);
         out.residual = g.h * sqrtT(swe / sw);
@@ -700,54 +710,6 @@ __device__ __forceinline__ void with_radius(int r, F&& f) {
     with_radius(r, f, std::make_integer_sequence<int, kMaxRadius>{});
 }
 
-// FP32 pass over one frame: one 256-lane workgroup per tile.  REJ: the rejection variant
-// of Eq. (11).
-template <int R, bool REJ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))
-void fit_tile_f32(FitDesc d, RefitList list) {
-    fit_tile_body<float, R, REJ>(d, blockIdx.x, blockIdx.y, 0u, list);
-}
-
-// FP64 pass over every pixel of one frame: 16x4 tiles.
-template <int R, bool REJ>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
-void fit_tile_f64(FitDesc d, RefitList list) {
-    fit_tile_body<double, R, REJ>(d, blockIdx.x, blockIdx.y, 0u, list);
-}
-
-// Persistent FP32 pass over a batch of frames.  Tiles are numbered frame after frame
-// (frames ordered by the host from most to least work per tile; first_tile[f] is the
-// number of the frame's first tile, first_tile[n] the total); every workgroup takes the
-// next tile number from counts[2] until none is left, so all frames share one launch.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))
-void fit_batch_f32(const FitDesc* frames, const uint32_t* first_tile, const uint32_t* header,
-                   RefitList list) {
-    __shared__ uint32_t next;
-    const uint32_t nf = header[0];
-    if (nf == 0) return;
-    const uint32_t total = first_tile[nf];
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(&list.counts[2], 1u);
-        __syncthreads();
-        const uint32_t t = __builtin_amdgcn_readfirstlane(next);
-        __syncthreads();
-        if (t >= total) break;
-        uint32_t lo = 0, hi = nf - 1;   // the frame holding tile t
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) / 2;
-            if (first_tile[mid] <= t) lo = mid; else hi = mid - 1;
-        }
-        lo = __builtin_amdgcn_readfirstlane(lo);
-        const FitDesc d = frames[lo];
-        const int local = static_cast<int>(t - first_tile[lo]);
-        const int across = tiles_across(d);
-        with_radius(d.radius, [&](auto rc) {
-            fit_tile_body<float, decltype(rc)::value>(d, local % across, local / across, lo, list);
-        });
-        __syncthreads();   // the next tile re-stages LDS
-    }
-}
-
 // ---------------------------------------------------------------------------- FP64 pass
 // The FP64 pass takes kChunk consecutive ranks at a time per wave from counts[3]; as the
 // ranks of an entry are padded to whole chunks, a chunk holds up to kChunk listed pixels
@@ -800,39 +762,6 @@ __device__ __forceinline__ uint32_t next_ranks(uint32_t* counter) {
     return __builtin_amdgcn_readfirstlane(base);
 }
 
-// FP64 pass over the listed pixels of one frame; one wave per workgroup, persistent
-// (waves loop until the ranks run out).  For each chunk the wave stages its tile plus halo
-// in LDS, as the FP32 pass did, and fits the chunk's pixels from there.
-template <int R, bool REJ>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
-void refit_f64(FitDesc d, RefitList list) {
-    extern __shared__ float2 region[];
-    const uint32_t ranks = list.counts[0], entries = list.counts[1];
-    const int tw = d.tile_w, th = 256 / tw;
-    const int halo = max(R, d.normal_radius);
-    const int pitch = tw + 2 * halo;
-    const int across = tiles_across(d);
-    const LaneGroup<kRefitLanes> grp{static_cast<int>(threadIdx.x % kRefitLanes)};
-    for (;;) {
-        const uint32_t base = next_ranks(&list.counts[3]);
-        if (base >= ranks) break;
-        const uint32_t slot = __builtin_amdgcn_readfirstlane(entry_of(list, entries, base));
-        const uint32_t tile = list.entries[slot] & 0xffffffu;
-        const int bx = static_cast<int>(tile % across) * tw, by = static_cast<int>(tile / across) * th;
-        stage_region(d, region, bx - halo, by - halo, pitch, th + 2 * halo);
-        const int t = listed_thread(list.masks + 4 * static_cast<size_t>(slot),
-                                    static_cast<int>(base - list.ranks[slot] + threadIdx.x / kRefitLanes));
-        if (t >= 0) {
-            const int lx = t % tw, ly = t / tw;
-            const float2* centre = region + (ly + halo) * pitch + (lx + halo);
-            const PixelFit<double> r = fit_pixel<double, R, kRefitLanes, REJ>(
-                d, LdsSource{centre, pitch}, bx + lx, by + ly, centre->x, d.residual != nullptr, grp);
-            if (grp.part == 0) store_pixel(d, static_cast<int64_t>(by + ly) * d.width + bx + lx, r);
-        }
-        __syncthreads();   // the next chunk re-stages the region
-    }
-}
-
 // FP64 pass over the listed pixels of a batch, reading the windows from the depth images.
 // Every chunk lies in one entry, hence one frame, so the frame's descriptor and window
 // radius are uniform across the wave.
@@ -850,137 +779,9 @@ __device__ __forceinline__ void refit_pixel_global(const FitDesc& d, uint32_t ti
     if (grp.part == 0) store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
-void refit_batch_f64(const FitDesc* frames, RefitList list) {
-    const uint32_t ranks = list.counts[0], entries = list.counts[1];
-    const LaneGroup<kRefitLanes> grp{static_cast<int>(threadIdx.x % kRefitLanes)};
-    for (;;) {
-        const uint32_t base = next_ranks(&list.counts[3]);
-        if (base >= ranks) break;
-        const uint32_t slot = __builtin_amdgcn_readfirstlane(entry_of(list, entries, base));
-        const uint32_t entry = __builtin_amdgcn_readfirstlane(list.entries[slot]);
-        const int t = listed_thread(list.masks + 4 * static_cast<size_t>(slot),
-                                    static_cast<int>(base - list.ranks[slot] + (threadIdx.x % 64) / kRefitLanes));
-        const FitDesc d = frames[entry >> 24];
-        if (t >= 0) {
-            with_radius(d.radius, [&](auto rc) {
-                refit_pixel_global<decltype(rc)::value>(d, entry & 0xffffffu, t, grp);
-            });
-        }
-    }
-}
-
-size_t lds_bytes(int tile_w, int tile_h, int halo) {
+inline size_t lds_bytes(int tile_w, int tile_h, int halo) {
     return sizeof(float2) * static_cast<size_t>(tile_w + 2 * halo) * static_cast<size_t>(tile_h + 2 * halo);
 }
 
-template <int R, bool REJ>
-hipError_t launch_variant(const FitDesc& d, const RefitList& list, int cus, hipStream_t st,
-                          hipEvent_t* ev) {
-    const int halo = R > d.normal_radius ? R : d.normal_radius;
-    hipError_t e;
-    if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
-    if (d.precision == 2) {
-        FitDesc d64 = d;
-        d64.tile_w = kTileW;
-        dim3 grid((d.width + kTileW - 1) / kTileW, (d.height + 3) / 4);
-        hipLaunchKernelGGL((fit_tile_f64<R, REJ>), grid, dim3(64), lds_bytes(kTileW, 4, halo), st, d64, list);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-        if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-        return hipSuccess;
-    }
-    const int tw = d.tile_w, th = 256 / tw;
-    const size_t lds = lds_bytes(tw, th, halo);
-    dim3 grid((d.width + tw - 1) / tw, (d.height + th - 1) / th);
-    hipLaunchKernelGGL((fit_tile_f32<R, REJ>), grid, dim3(256), lds, st, d, list);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-    if (d.precision == 0) {
-        hipLaunchKernelGGL((refit_f64<R, REJ>), dim3(16 * cus), dim3(64), lds, st, d, list);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-    return hipSuccess;
-}
-
-template <int R>
-hipError_t launch_radius(const FitDesc& d, const RefitList& list, int cus, hipStream_t st,
-                         hipEvent_t* ev) {
-    return d.reject ? launch_variant<R, true>(d, list, cus, st, ev)
-                    : launch_variant<R, false>(d, list, cus, st, ev);
-}
-
-template <int... Rs>
-hipError_t dispatch_radius(int r, const FitDesc& d, const RefitList& list, int cus,
-                           hipStream_t st, hipEvent_t* ev, std::integer_sequence<int, Rs...>) {
-    hipError_t e = hipErrorInvalidValue;
-    (void)((r == Rs + 1 ? (e = launch_radius<Rs + 1>(d, list, cus, st, ev), true) : false) || ...);
-    return e;
-}
-
 }  // namespace
-
-int64_t refit_capacity(int width, int height, int tile_w) {
-    const int64_t th = 256 / tile_w;
-    return ((width + tile_w - 1) / tile_w) * static_cast<int64_t>((height + th - 1) / th);
-}
-
-bool valid_tile_width(int tile_w) {
-    return tile_w == 8 || tile_w == 16 || tile_w == 32 || tile_w == 64;
-}
-
-size_t refit_list_bytes(int64_t tiles) {
-    return static_cast<size_t>(tiles) * (4 * sizeof(uint64_t) + 2 * sizeof(uint32_t));
-}
-
-RefitList refit_list(void* storage, int64_t tiles, uint32_t* counts) {
-    char* p = static_cast<char*>(storage);
-    RefitList l;
-    l.masks = reinterpret_cast<uint64_t*>(p);
-    l.entries = reinterpret_cast<uint32_t*>(p + 4 * sizeof(uint64_t) * static_cast<size_t>(tiles));
-    l.ranks = l.entries + tiles;
-    l.counts = counts;
-    return l;
-}
-
-hipError_t launch_fit(const FitDesc& d, const RefitList& list, int cus, hipStream_t stream,
-                      hipEvent_t* events) {
-    if (d.precision != 2) {
-        hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, list.counts);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return dispatch_radius(d.radius, d, list, cus, stream, events,
-                           std::make_integer_sequence<int, kMaxRadius>{});
-}
-
-size_t batch_lds_bytes() {
-    // largest staging region over the supported tile shapes at the largest halo
-    size_t m = 0;
-    for (int tw = 8; tw <= 64; tw *= 2) {
-        const size_t b = lds_bytes(tw, 256 / tw, kMaxRadius);
-        m = b > m ? b : m;
-    }
-    return m;
-}
-
-hipError_t launch_fit_batch(const FitDesc* frames, const uint32_t* first_tile,
-                            const uint32_t* header, int workgroups, const RefitList& list,
-                            hipStream_t stream, hipEvent_t* events) {
-    hipError_t e;
-    hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, list.counts);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const size_t lds = batch_lds_bytes();
-    if (events && (e = hipEventRecord(events[0], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(fit_batch_f32, dim3(workgroups), dim3(256), lds, stream, frames, first_tile,
-                       header, list);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (events && (e = hipEventRecord(events[1], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(refit_batch_f64, dim3(workgroups), dim3(256), 0, stream, frames, list);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (events && (e = hipEventRecord(events[2], stream)) != hipSuccess) return e;
-    return hipSuccess;
-}
-
 }  // namespace qc

@@ -1,0 +1,41 @@
+// fit_frame.hip -- per-frame launches (default weights), the list helpers, and the entry
+// that picks the variant.
+#include "fit_frame.h"
+
+namespace qc {
+
+int64_t refit_capacity(int width, int height, int tile_w) {
+    const int64_t th = 256 / tile_w;
+    return ((width + tile_w - 1) / tile_w) * static_cast<int64_t>((height + th - 1) / th);
+}
+
+bool valid_tile_width(int tile_w) {
+    return tile_w == 8 || tile_w == 16 || tile_w == 32 || tile_w == 64;
+}
+
+size_t refit_list_bytes(int64_t tiles) {
+    return static_cast<size_t>(tiles) * (4 * sizeof(uint64_t) + 2 * sizeof(uint32_t));
+}
+
+RefitList refit_list(void* storage, int64_t tiles, uint32_t* counts) {
+    char* p = static_cast<char*>(storage);
+    RefitList l;
+    l.masks = reinterpret_cast<uint64_t*>(p);
+    l.entries = reinterpret_cast<uint32_t*>(p + 4 * sizeof(uint64_t) * static_cast<size_t>(tiles));
+    l.ranks = l.entries + tiles;
+    l.counts = counts;
+    return l;
+}
+
+hipError_t launch_fit(const FitDesc& d, const RefitList& list, int cus, hipStream_t stream,
+                      hipEvent_t* events) {
+    if (d.precision != 2) {
+        hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, list.counts);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return d.reject ? launch_frame_reject(d, list, cus, stream, events)
+                    : launch_frame<false>(d, list, cus, stream, events);
+}
+
+}  // namespace qc
