@@ -41,7 +41,7 @@ constexpr int kTileW = 16;
 constexpr float kRejectMargin = 2e-5f;
 
 #ifndef QC_F32_WAVES_PER_EU
-#define QC_F32_WAVES_PER_EU 4
+#define QC_F32_WAVES_PER_EU 3
 #endif
 #ifndef QC_F64_WAVES_PER_EU
 #define QC_F64_WAVES_PER_EU 3
@@ -49,6 +49,7 @@ constexpr float kRejectMargin = 2e-5f;
 #ifndef QC_F64_UNROLL
 #define QC_F64_UNROLL 3
 #endif
+
 
 // ---------------------------------------------------------------------------- scalars
 template <typename T> __device__ __forceinline__ T fmaT(T a, T b, T c);
@@ -194,9 +195,13 @@ struct LaneGroup {
 // unrolled for FP32 (U = 0); FP64 unrolls it U neighbours at a time (U >= 2), so that the
 // dependency chains of several neighbours interleave, or keeps it rolled (U = 1), to stay
 // within the register file.
-template <int RC, int U, int NP, typename Src, typename F>
+struct NoRowEnd {
+    __device__ __forceinline__ void operator()() const {}
+};
+
+template <int RC, int U, int NP, typename Src, typename F, typename G = NoRowEnd>
 __device__ __forceinline__ void for_window(const Src& src, int radius, const LaneGroup<NP>& grp,
-                                           F&& f) {
+                                           F&& f, G&& row_end = G{}) {
     const int r = RC > 0 ? RC : radius;
     const int first = NP > 1 ? -r + grp.part : -r;
     // The row loop stays rolled: unrolled, a short body (e.g. the mean of e^2 ahead of the
@@ -207,6 +212,7 @@ __device__ __forceinline__ void for_window(const Src& src, int radius, const Lan
             auto row = src.row(dv);
 #pragma unroll
             for (int du = -RC; du <= RC; ++du) f(row[du], du, dv);
+            row_end();
         }
     } else if constexpr (U >= 2) {
 #pragma unroll 1
@@ -214,6 +220,7 @@ __device__ __forceinline__ void for_window(const Src& src, int radius, const Lan
             auto row = src.row(dv);
 #pragma unroll U
             for (int du = -r; du <= r; ++du) f(row[du], du, dv);
+            row_end();
         }
     } else {
         // rolled row: the next sample's LDS read is issued before this one is used
@@ -226,9 +233,17 @@ __device__ __forceinline__ void for_window(const Src& src, int radius, const Lan
                 f(cur, du, dv);
                 cur = nxt;
             }
+            row_end();
         }
     }
 }
+
+// The 26 distinct sums of the normal equations as products of the seven scaled terms
+// v = sqrt(w) (J0, J1, 1, sx^2, sx sy, sy^2, e): H00 H01 H03 H04 H05 H11 H13 H14 H15 H33
+// H34 H35 H45 H55, S0..S5 (with v2 = sqrt(w)), G0..G5 (with v6 = sqrt(w) e).
+constexpr int kSums = 26;
+constexpr int kSumA[kSums] = {0, 0, 0, 0, 0, 1, 1, 1, 1, 3, 3, 3, 4, 5, 0, 1, 2, 3, 4, 5, 0, 1, 2, 3, 4, 5};
+constexpr int kSumB[kSums] = {0, 1, 3, 4, 5, 1, 3, 4, 5, 3, 4, 5, 5, 5, 2, 2, 2, 2, 2, 2, 6, 6, 6, 6, 6, 6};
 
 // The pixel's fit, Section 3.2: initial normal (Eq. (7)), frame set-up, fixed number of
 // re-weighted Gauss-Newton steps (Eqs. (8)-(11)), curvatures, refined normal.
@@ -368,16 +383,24 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
         // FP32: the closest any decision e^2 < R came to the bound; a pixel with one too
         // close to be sure of is left to FP64
         Real gap = Real(INFINITY);
-        // accumulators: Hij = sum ji jj with j = sqrt(w) * (J0, J1, -1, sx^2, sx sy, sy^2);
-        // S_i = sum ji sqrt(w) (column 2 up to sign); Gi = sum ji sqrt(w) e.
-        // The sums are accumulated in FP64 whatever the per-neighbour precision: FP32
-        // accumulation of 225 terms is the dominant rounding error of the FP32 fit.
-        Acc H00 = 0, H01 = 0, H03 = 0, H04 = 0, H05 = 0, H11 = 0, H13 = 0, H14 = 0, H15 = 0;
-        Acc H33 = 0, H34 = 0, H35 = 0, H45 = 0, H55 = 0;
-        Acc S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0;
-        Acc G0 = 0, G1 = 0, G2 = 0, G3 = 0, G4 = 0, G5 = 0;
+        // Normal-equation sums (kSumA / kSumB).  The FP32 path sums each window row (2r+1
+        // terms) in FP32 and adds the row sums in FP64: one sequence of FP32 additions over
+        // the whole window (225 terms at r = 7) is the dominant rounding error of an FP32
+        // fit, while a row's error stays near that of the terms themselves; per neighbour
+        // this takes 26 FP32 FMAs instead of 7 conversions and 26 FP64 FMAs.  The FP64 path
+        // accumulates in FP64 throughout.
+        constexpr bool row_sums = sizeof(Real) == 4;
+        Acc sum[kSums];
+        Real rsum[kSums];
+#pragma unroll
+        for (int k = 0; k < kSums; ++k) {
+            sum[k] = 0;
+            rsum[k] = 0;
+        }
         for_window<RC, sizeof(Real) == 8 ? QC_F64_UNROLL : 0>(src, radius, grp, [&](float2 t, int du, int dv) {
-            // s = R' m with m = (du D, dv D, D - Dc), as (R'x0 du + R'x1 dv) D + R'x2 (D - Dc)
+            // s = R' m with m = (du D, dv D, D - Dc), as (R'x0 du + R'x1 dv) D + R'x2 (D - Dc):
+            // each term is rounded relative to itself, so a neighbour close to the centre
+            // (small D - Dc) keeps its small coordinates accurate
             const Real D = Real(t.x);
             const Real dD = D - g.Dc;
             const Real fdu = Real(du), fdv = Real(dv);
@@ -397,33 +420,37 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             const Real rw = rsqrtT(fmaT(e, e, c));          // sqrt of the weight, Eq. (11)
             const Real J0 = -fmaT(cp, sz2, sy);             // de/dtheta_x
             const Real J1 = fmaT(ap, sz2, sx);              // de/dtheta_y
-            const Real j0r = rw * J0, j1r = rw * J1;
             const Real xr = rw * sx, yr = rw * sy;
-            const Real j3r = xr * sx, j4r = xr * sy, j5r = yr * sy, jer = rw * e;
-            const Acc j0 = Acc(j0r), j1 = Acc(j1r), wr = Acc(rw);
-            const Acc j3 = Acc(j3r), j4 = Acc(j4r), j5 = Acc(j5r), je = Acc(jer);
-            H00 = fmaT(j0, j0, H00); H01 = fmaT(j0, j1, H01); H03 = fmaT(j0, j3, H03);
-            H04 = fmaT(j0, j4, H04); H05 = fmaT(j0, j5, H05);
-            H11 = fmaT(j1, j1, H11); H13 = fmaT(j1, j3, H13); H14 = fmaT(j1, j4, H14);
-            H15 = fmaT(j1, j5, H15);
-            H33 = fmaT(j3, j3, H33); H34 = fmaT(j3, j4, H34); H35 = fmaT(j3, j5, H35);
-            H45 = fmaT(j4, j5, H45); H55 = fmaT(j5, j5, H55);
-            S0 = fmaT(j0, wr, S0); S1 = fmaT(j1, wr, S1); S2 = fmaT(wr, wr, S2);
-            S3 = fmaT(j3, wr, S3); S4 = fmaT(j4, wr, S4); S5 = fmaT(j5, wr, S5);
-            G0 = fmaT(j0, je, G0); G1 = fmaT(j1, je, G1); G2 = fmaT(wr, je, G2);
-            G3 = fmaT(j3, je, G3); G4 = fmaT(j4, je, G4); G5 = fmaT(j5, je, G5);
+            const Real v[7] = {rw * J0, rw * J1, rw, xr * sx, xr * sy, yr * sy, rw * e};
+            if constexpr (row_sums) {
+#pragma unroll
+                for (int k = 0; k < kSums; ++k) rsum[k] = fmaT(v[kSumA[k]], v[kSumB[k]], rsum[k]);
+            } else {
+                Acc va[7];
+#pragma unroll
+                for (int i = 0; i < 7; ++i) va[i] = Acc(v[i]);
+#pragma unroll
+                for (int k = 0; k < kSums; ++k) sum[k] = fmaT(va[kSumA[k]], va[kSumB[k]], sum[k]);
+            }
+        }, [&]() {
+            if constexpr (row_sums) {
+#pragma unroll
+                for (int k = 0; k < kSums; ++k) {
+                    sum[k] += Acc(rsum[k]);
+                    rsum[k] = 0;
+                }
+            }
         });
         if constexpr (REJ && sizeof(Real) == 4) near |= thresh < Real(INFINITY) && gap <= Real(kRejectMargin) * thresh;
         if constexpr (NP > 1) {
-            H00 = grp.sum(H00); H01 = grp.sum(H01); H03 = grp.sum(H03); H04 = grp.sum(H04);
-            H05 = grp.sum(H05); H11 = grp.sum(H11); H13 = grp.sum(H13); H14 = grp.sum(H14);
-            H15 = grp.sum(H15); H33 = grp.sum(H33); H34 = grp.sum(H34); H35 = grp.sum(H35);
-            H45 = grp.sum(H45); H55 = grp.sum(H55);
-            S0 = grp.sum(S0); S1 = grp.sum(S1); S2 = grp.sum(S2);
-            S3 = grp.sum(S3); S4 = grp.sum(S4); S5 = grp.sum(S5);
-            G0 = grp.sum(G0); G1 = grp.sum(G1); G2 = grp.sum(G2);
-            G3 = grp.sum(G3); G4 = grp.sum(G4); G5 = grp.sum(G5);
+#pragma unroll
+            for (int k = 0; k < kSums; ++k) sum[k] = grp.sum(sum[k]);
         }
+        const Acc H00 = sum[0], H01 = sum[1], H03 = sum[2], H04 = sum[3], H05 = sum[4];
+        const Acc H11 = sum[5], H13 = sum[6], H14 = sum[7], H15 = sum[8];
+        const Acc H33 = sum[9], H34 = sum[10], H35 = sum[11], H45 = sum[12], H55 = sum[13];
+        const Acc S0 = sum[14], S1 = sum[15], S2 = sum[16], S3 = sum[17], S4 = sum[18], S5 = sum[19];
+        const Acc G0 = sum[20], G1 = sum[21], G2 = sum[22], G3 = sum[23], G4 = sum[24], G5 = sum[25];
         // Normal equations of Eq. (10) for the parameters (theta_x, theta_y, t_z, A, B, C):
         // J2 = -1, and J3, J5 carry a factor 1/2 (de/dA = qx^2/2, de/dC = qy^2/2).
         // H44 = sum w qx^2 qy^2 = 4 * (H35 scaled) -- same sum as sx^2 * sy^2.

@@ -12,11 +12,11 @@ hipError_t launch_frame_reject(const FitDesc& d, const RefitList& list, int cus,
 
 namespace {
 
-// FP32 pass over one frame: one 256-lane workgroup per tile.  REJ: the rejection variant
-// of Eq. (11), whose unrolled rows need a few more registers than the 128 of 4 waves per
-// SIMD (the pass runs as fast at 3 or 2 waves per SIMD).
+// FP32 pass over one frame: one 256-lane workgroup per tile (REJ: the rejection variant
+// of Eq. (11)).  Its unrolled rows with FP32 row sums need ~150 registers: 3 waves per
+// SIMD (the pass runs as fast at 2, 3 or 4 waves per SIMD).
 template <int R, bool REJ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(REJ ? 3 : QC_F32_WAVES_PER_EU)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))
 void fit_tile_f32(FitDesc d, RefitList list) {
     fit_tile_body<float, R, REJ>(d, blockIdx.x, blockIdx.y, 0u, list);
 }
