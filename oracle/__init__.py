@@ -19,7 +19,7 @@ _lib = None
 class OracleParams(ctypes.Structure):
     _fields_ = [("radius", ctypes.c_int32), ("normal_radius", ctypes.c_int32),
                 ("iterations", ctypes.c_int32), ("reject", ctypes.c_int32),
-                ("k", ctypes.c_double)]
+                ("k", ctypes.c_double), ("stride", ctypes.c_int32)]
 
 
 def _load():
@@ -60,20 +60,20 @@ def _ptr(a: Optional[np.ndarray], ctype=ctypes.c_double):
 
 
 def params(radius: int, iterations: int, k: float, normal_radius: int = 3,
-           reject: bool = False) -> OracleParams:
+           reject: bool = False, stride: int = 1) -> OracleParams:
     return OracleParams(int(radius), int(normal_radius), int(iterations), int(bool(reject)),
-                        float(k))
+                        float(k), int(stride))
 
 
 def fit_image(depth_m: np.ndarray, fx: float, fy: float, cx: float, cy: float,
               radius: int, iterations: int, k: float, normal_radius: int = 3,
-              reject: bool = False, threads: int = 0) -> dict:
+              reject: bool = False, threads: int = 0, stride: int = 1) -> dict:
     """Fits every pixel.  Returns dict of k1, k2, normal (H,W,3), residual, flags."""
     d = np.ascontiguousarray(depth_m, dtype=np.float64)
     H, W = d.shape
     out = dict(k1=np.empty((H, W)), k2=np.empty((H, W)), normal=np.empty((H, W, 3)),
                residual=np.empty((H, W)), flags=np.empty((H, W), dtype=np.uint8))
-    p = params(radius, iterations, k, normal_radius, reject)
+    p = params(radius, iterations, k, normal_radius, reject, stride)
     rc = _load().oracle_fit_image(_ptr(d), W, H, fx, fy, cx, cy, ctypes.byref(p),
                                   _ptr(out["k1"]), _ptr(out["k2"]), _ptr(out["normal"]),
                                   _ptr(out["residual"]), _ptr(out["flags"], ctypes.c_uint8),
@@ -85,7 +85,7 @@ def fit_image(depth_m: np.ndarray, fx: float, fy: float, cx: float, cy: float,
 
 def fit_pixels(depth_m: np.ndarray, pixels: np.ndarray, fx: float, fy: float, cx: float,
                cy: float, radius: int, iterations: int, k: float, normal_radius: int = 3,
-               reject: bool = False, threads: int = 0) -> dict:
+               reject: bool = False, threads: int = 0, stride: int = 1) -> dict:
     """Fits only the listed pixels (linear indices v*W+u)."""
     d = np.ascontiguousarray(depth_m, dtype=np.float64)
     H, W = d.shape
@@ -93,7 +93,7 @@ def fit_pixels(depth_m: np.ndarray, pixels: np.ndarray, fx: float, fy: float, cx
     n = px.size
     out = dict(k1=np.empty(n), k2=np.empty(n), normal=np.empty((n, 3)), residual=np.empty(n),
                flags=np.empty(n, dtype=np.uint8))
-    p = params(radius, iterations, k, normal_radius, reject)
+    p = params(radius, iterations, k, normal_radius, reject, stride)
     rc = _load().oracle_fit_pixels(_ptr(d), W, H, fx, fy, cx, cy, ctypes.byref(p),
                                    _ptr(px, ctypes.c_int64), n, _ptr(out["k1"]), _ptr(out["k2"]),
                                    _ptr(out["normal"]), _ptr(out["residual"]),

@@ -22,7 +22,10 @@
  *     sqrt(T1^2 - AC + B^2) but free of cancellation;
  *   - with rejection on, R = 2 * (unweighted mean of e^2 over the patch); nothing is
  *     rejected when that mean is zero;
- *   - the reported residual is sqrt(sum w e^2 / sum w) at the final parameters.
+ *   - the reported residual is sqrt(sum w e^2 / sum w) at the final parameters;
+ *   - the large patch "sparsely sampled" for the timings of Section 4 takes the pixels
+ *     at offsets that are multiples of a stride s from the centre, within +-r (the
+ *     stride is not given; s = 1 samples every pixel); the normal window stays dense.
  */
 #include "oracle.h"
 
@@ -268,6 +271,7 @@ static int check_params(const oracle_params* p) {
     if (p->normal_radius < 1 || (2 * p->normal_radius + 1) * (2 * p->normal_radius + 1) > MAXPTS) return 0;
     if (p->iterations < 0) return 0;
     if (!(p->k > 0.0)) return 0;
+    if (p->stride < 1 || p->stride > p->radius) return 0;
     return 1;
 }
 
@@ -298,10 +302,11 @@ static void fit_pixel(const double* depth, int W, int Hh, double fx, double fy, 
     double n0[3];
     if (!initial_normal((const double (*)[3])pts, n, n0)) return;
 
-    int r = prm->radius;
+    int r = prm->radius, s = prm->stride, m = r / s;
     n = 0;
-    for (int dv = -r; dv <= r; ++dv)
-        for (int du = -r; du <= r; ++du) {
+    for (int j = -m; j <= m; ++j)
+        for (int i = -m; i <= m; ++i) {
+            int du = i * s, dv = j * s;
             int uu = u + du, vv = v + dv;
             if (uu < 0 || vv < 0 || uu >= W || vv >= Hh) continue;
             double Z = depth[(size_t)vv * W + uu];

@@ -25,6 +25,9 @@ typedef struct {
     int32_t iterations;     /* T: fixed number of re-weighted Gauss-Newton steps */
     int32_t reject;         /* 0: weights k/(k+e^2); 1: also zero points with e^2 >= 2*MSE */
     double k;               /* robust constant of Eq. (11), m^2, > 0 */
+    int32_t stride;         /* s >= 1: the fit window samples the pixels at offsets that are
+                               multiples of s from the centre, within +-r (the paper's
+                               sparsely sampled large patch, Section 4); 1 = every pixel */
 } oracle_params;
 
 /* Per-pixel result flags. */

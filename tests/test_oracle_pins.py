@@ -409,3 +409,78 @@ def test_rejection_filter_removes_gross_outlier():
     keep = oracle.fit_patch(bad, ci, n0, iterations=8, k=1e-6, reject=False)
     assert abs(rej["k1"] - ev[1]) < 1e-8 and abs(rej["k2"] - ev[0]) < 1e-8
     assert abs(keep["k1"] - ev[1]) + abs(keep["k2"] - ev[0]) > 1e-6
+
+
+# ---- strided ("sparsely sampled") patch: the large patch of the timings of Section 4 ----
+
+def _window_points(sc, u, v, r, s):
+    """Back-projected points of the pixels at offsets (i s, j s), |i s|, |j s| <= r, inside
+    the image and with depth, in raster order; gathered here with plain loops, apart
+    from the oracle.  Returns the points and the index of the centre."""
+    c = sc.camera
+    H, W = sc.depth_m.shape
+    pts, centre = [], None
+    m = r // s
+    for j in range(-m, m + 1):
+        for i in range(-m, m + 1):
+            uu, vv = u + i * s, v + j * s
+            if not (0 <= uu < W and 0 <= vv < H):
+                continue
+            Z = sc.depth_m[vv, uu]
+            if not Z > 0:
+                continue
+            if i == 0 and j == 0:
+                centre = len(pts)
+            pts.append([Z * (uu - c.cx) / c.fx, Z * (vv - c.cy) / c.fy, Z])
+    return np.array(pts), centre
+
+
+@pytest.mark.parametrize("r,s", [(6, 2), (18, 3), (9, 4), (7, 7)])
+def test_strided_window_is_the_subsampled_point_set(r, s):
+    """With stride s the fit of a pixel equals the point-set fit of its window sampled at
+    multiples of s (initial normal: the least-squares plane of the dense 7x7 window),
+    on noisy input, including pixels whose window leaves the image."""
+    cam = scenes.Camera(80, 60, 70.0, 70.0, 39.5, 29.5)
+    sc = scenes.cluttered_scene(cam, seed_frame=21, config_index=5)
+    o = oracle.fit_image(sc.depth_m, *_cam(sc), radius=r, iterations=4, k=1e-5, stride=s)
+    checked = 0
+    for (u, v) in [(40, 30), (12, 47), (66, 9), (2, 3), (79, 59), (33, 20), (55, 41)]:
+        if not sc.depth_m[v, u] > 0:
+            continue
+        pts, ci = _window_points(sc, u, v, r, s)
+        n0 = _lstsq_normal(_window_points(sc, u, v, 3, 1)[0])
+        f = oracle.fit_patch(pts, ci, n0, iterations=4, k=1e-5)
+        assert bool(f["valid"]) == bool(o["flags"][v, u] == 1)
+        if f["valid"]:
+            for key in ("k1", "k2"):
+                assert abs(f[key] - o[key][v, u]) <= 1e-9 * max(1.0, abs(f[key]))
+            np.testing.assert_allclose(f["normal"], o["normal"][v, u], atol=1e-10)
+            checked += 1
+    assert checked >= 5
+
+
+@pytest.mark.parametrize("r,s", [(6, 2), (9, 3)])
+def test_exact_quadric_recovered_with_stride(r, s):
+    """A noiseless parabolic patch is still fitted exactly at its vertex from the
+    subsampled window."""
+    rng = np.random.default_rng(300 + r)
+    for trial in range(4):
+        A, B, C = rng.uniform(-20, 20, 3)
+        z = np.array([rng.uniform(-0.4, 0.4), rng.uniform(-0.4, 0.4), 1.0])
+        rot = _frame_with_z(z, rng.uniform(0, 2 * np.pi))
+        sc, (u, v) = scenes.quadric_vertex_scene(A, B, C, rot, distance=0.8, size=2 * r + 9, f=300.0)
+        W = sc.camera.width
+        o = oracle.fit_pixels(sc.depth_m, np.array([v * W + u]), *_cam(sc), radius=r,
+                              iterations=10, k=1e-5, stride=s)
+        ev = np.linalg.eigvalsh([[A, B], [B, C]])
+        assert o["flags"][0] == 1
+        assert abs(o["k1"][0] - ev[1]) < 1e-8 * max(1, abs(ev[1]))
+        assert abs(o["k2"][0] - ev[0]) < 1e-8 * max(1, abs(ev[0]))
+
+
+def test_stride_one_is_the_dense_window():
+    sc = scenes.sphere_on_plane(noise=True)
+    a = oracle.fit_image(sc.depth_m, *_cam(sc), radius=3, iterations=3, k=1e-5)
+    b = oracle.fit_image(sc.depth_m, *_cam(sc), radius=3, iterations=3, k=1e-5, stride=1)
+    for key in ("k1", "k2", "normal", "residual", "flags"):
+        assert np.array_equal(a[key], b[key], equal_nan=True)
