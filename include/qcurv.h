@@ -90,6 +90,11 @@ typedef struct {
     int32_t tile_width;      /* FP32 pass tile: 8, 16, 32 or 64 pixels wide (256 pixels);
                                 0 = the width qc_tune recorded for this frame size, radius
                                 and iteration count, else 16.  Results do not depend on it. */
+    int32_t stride;          /* 1..radius: the fit window takes the pixels at offsets that
+                                are multiples of `stride` within +-radius (the sparsely
+                                sampled large patch of the timings of Section 4), i.e.
+                                (2 floor(radius/stride) + 1)^2 samples; the initial-normal
+                                window stays dense.  1 (default) = every pixel. */
 } qc_params;
 
 typedef struct {
@@ -140,7 +145,7 @@ typedef struct {
  * launch (MIXED), replayed from a HIP graph the context captures once.  Each item's
  * outputs equal, bit for bit, those of qc_fit on the same item.  All items must use the
  * same precision, MIXED or FP32 (FP64 frames go through qc_fit).  A batch holding an item
- * with reject = 1 runs as per-frame launches in item order instead.  At most two batches
+ * with reject = 1 or stride > 1 runs as per-frame launches in item order instead.  At most two batches
  * are in flight per context; a third call first waits for the oldest.  Asynchronous on
  * `stream`; the items array itself may be reused as soon as the call returns. */
 qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, void* stream);

@@ -40,7 +40,8 @@ class Params(ctypes.Structure):
                 ("iterations", ctypes.c_int32), ("k", ctypes.c_float),
                 ("reject", ctypes.c_int32), ("depth_scale", ctypes.c_float),
                 ("precision", ctypes.c_int32), ("cond_max", ctypes.c_float),
-                ("step_max", ctypes.c_float), ("tile_width", ctypes.c_int32)]
+                ("step_max", ctypes.c_float), ("tile_width", ctypes.c_int32),
+                ("stride", ctypes.c_int32)]
 
 
 class Frame(ctypes.Structure):

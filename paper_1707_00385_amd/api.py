@@ -22,9 +22,10 @@ def default_params() -> _lib.Params:
 def make_params(radius: int = 7, iterations: int = 5, k: float = 1e-5, normal_radius: int = 3,
                 depth_scale: float = 1e-3, precision: str = "mixed",
                 cond_max: Optional[float] = None, step_max: Optional[float] = None,
-                tile_width: int = 0, reject: int = 0) -> _lib.Params:
+                tile_width: int = 0, reject: int = 0, stride: int = 1) -> _lib.Params:
     p = default_params()
     p.reject = int(reject)
+    p.stride = int(stride)
     p.radius = int(radius)
     p.iterations = int(iterations)
     p.k = float(k)

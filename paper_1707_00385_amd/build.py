@@ -13,9 +13,11 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libqcurv.so")
 
-# Kernel translation units (compiled in parallel: the per-frame kernels with and without
-# rejection and the batched kernels each instantiate every window radius) and the host side.
-SOURCES = ["fit_frame.hip", "fit_frame_reject.hip", "fit_batch.hip", "qcurv_api.cpp", "serve.cpp"]
+# Kernel translation units (compiled in parallel: the per-frame kernels for each of
+# default / rejection / strided / strided + rejection, and the batched kernels, each
+# instantiate every window size) and the host side.
+SOURCES = ["fit_frame.hip", "fit_frame_reject.hip", "fit_frame_strided.hip",
+           "fit_frame_strided_reject.hip", "fit_batch.hip", "qcurv_api.cpp", "serve.cpp"]
 
 # Packed FP32 instructions are disabled: the compiler would otherwise form them from
 # scalar float code.  fp-contract is off so that every fused multiply-add is the one

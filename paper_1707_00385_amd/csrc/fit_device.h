@@ -102,6 +102,19 @@ struct LdsSource {
     int pitch;              // entries per LDS row
     __device__ __forceinline__ LdsRow row(int dv) const { return LdsRow{centre + dv * pitch}; }
 };
+// The window sampled at a stride: row(j)[i] is pixel (u + i step, v + j step).
+struct LdsStridedRow {
+    const float2* p;
+    int step;
+    __device__ __forceinline__ float2 operator[](int i) const { return p[i * step]; }
+};
+struct LdsStridedSource {
+    const float2* centre;
+    int pitch, step;
+    __device__ __forceinline__ LdsStridedRow row(int j) const {
+        return LdsStridedRow{centre + j * step * pitch, step};
+    }
+};
 // Neighbourhood read straight from the depth image (L2-resident), with the same (D, c)
 // pairs as the LDS copy.  The read is branch-free, so that the window loop stays straight-
 // line code whose loads can be issued ahead: coordinates are clamped into the image, a
@@ -247,16 +260,22 @@ constexpr int kSumB[kSums] = {0, 1, 3, 4, 5, 1, 3, 4, 5, 3, 4, 5, 5, 5, 2, 2, 2,
 
 // The pixel's fit, Section 3.2: initial normal (Eq. (7)), frame set-up, fixed number of
 // re-weighted Gauss-Newton steps (Eqs. (8)-(11)), curvatures, refined normal.
-template <typename Real, int RC, int NP = 1, bool REJ = false, typename Src>
-__device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int v, float Dc_f,
-                                    bool want_residual, LaneGroup<NP> grp = LaneGroup<NP>{0}) {
+// `nsrc` reads the (dense) initial-normal window, `src` the fit window; with STR the fit
+// window is sampled at the stride d.stride (src indexes samples, not pixels), which is
+// folded into the first two columns of the per-iteration map R'.
+template <typename Real, int RC, int NP = 1, bool REJ = false, bool STR = false, typename NSrc,
+          typename Src>
+__device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Src& src, int u, int v,
+                                    float Dc_f, bool want_residual,
+                                    LaneGroup<NP> grp = LaneGroup<NP>{0}) {
     PixelFit<Real> out;
     const Real nan = Real(NAN);
     out.k1 = out.k2 = out.residual = nan;
     out.n[0] = out.n[1] = out.n[2] = nan;
     out.flags = 0;
     using Acc = double;   // normal-equation sums and the 6x6 solve
-    const int radius = RC > 0 ? RC : d.radius;
+    const int radius = RC > 0 ? RC : d.radius;   // samples either side of the centre
+    const int step = STR ? d.stride : 1;        // pixels between samples
     const bool fp32 = sizeof(Real) == 4;
 
     // ---- geometry (Eq. (5) centring on native samples, lengths in units of h)
@@ -277,7 +296,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
     //      with mean-centred sums M, v; n0 = (-a, -b, 1) / sqrt(1 + a^2 + b^2)
     const int rn = d.normal_radius;
     Real cnt = 0, mx_ = 0, my_ = 0, mz_ = 0;
-    for_window<0, 1>(src, rn, grp, [&](float2 t, int du, int dv) {
+    for_window<0, 1>(nsrc, rn, grp, [&](float2 t, int du, int dv) {
         const Real ok = present(t) ? Real(1) : Real(0);
         const Real D = Real(t.x), dD = D - g.Dc;
         const Real px = fmaT(g.g00, Real(du) * D, g.g02 * dD);
@@ -295,7 +314,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
     if (cnt < Real(3)) return out;
     mx_ /= cnt; my_ /= cnt; mz_ /= cnt;
     Real M00 = 0, M01 = 0, M11 = 0, v0 = 0, v1 = 0;
-    for_window<0, 1>(src, rn, grp, [&](float2 t, int du, int dv) {
+    for_window<0, 1>(nsrc, rn, grp, [&](float2 t, int du, int dv) {
         const Real ok = present(t) ? Real(1) : Real(0);
         const Real D = Real(t.x), dD = D - g.Dc;
         const Real px = fmaT(g.g00, Real(du) * D, g.g02 * dD) - mx_;
@@ -346,7 +365,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
     Acc kappa_max = 0, last_step = 0;
     bool near = false;                    // an FP32 rejection decision was too close to call
     // window half-extent r Z_c / fx in units of h
-    const Acc hwin = Acc(radius) * Acc(g.Dc) * Acc(s) / Acc(fx) * Acc(g.ih);
+    const Acc hwin = Acc(radius * step) * Acc(g.Dc) * Acc(s) / Acc(fx) * Acc(g.ih);
 
     for (int it = 0; it < d.iterations; ++it) {
         // R' = R G: maps m straight to the rotated, scaled, centred point s = R p'/h.
@@ -358,6 +377,10 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             Rp[i][0] = f * R[i][0] * g.g00;
             Rp[i][1] = f * R[i][1] * g.g11;
             Rp[i][2] = f * fmaT(R[i][0], g.g02, fmaT(R[i][1], g.g12, R[i][2] * g.g22));
+            if constexpr (STR) {
+                Rp[i][0] *= Real(step);
+                Rp[i][1] *= Real(step);
+            }
         }
         const Real Ah = Real(0.5) * A, Bh = Real(0.5) * B, Ch = Real(0.5) * C;
         // Rejection (Eq. (11) with R = 2 MSE, Section 3.2.3): R from the unweighted mean
@@ -560,6 +583,10 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const Src& src, int u, int
             Rp[i][0] = R[i][0] * g.g00;
             Rp[i][1] = R[i][1] * g.g11;
             Rp[i][2] = fmaT(R[i][0], g.g02, fmaT(R[i][1], g.g12, R[i][2] * g.g22));
+            if constexpr (STR) {
+                Rp[i][0] *= Real(step);
+                Rp[i][1] *= Real(step);
+            }
         }
         const Real Ah = Real(0.5) * A, Bh = Real(0.5) * B, Ch = Real(0.5) * C;
         Real thresh = Real(INFINITY);
@@ -674,13 +701,13 @@ __device__ __forceinline__ int tiles_across(const FitDesc& d) {
 // MIXED precision the pixels whose FP32 fit is unreliable are not stored but listed: one
 // list entry for the tile with a 256-bit mask of them (bit t = thread t = pixel
 // (t % tw, t / tw)) and the rank of its first listed pixel.
-template <typename Real, int R, bool REJ = false>
+template <typename Real, int R, bool REJ = false, bool STR = false>
 __device__ __forceinline__ void fit_tile_body(const FitDesc& d, int tx, int ty, uint32_t frame,
                                               const RefitList& list) {
     extern __shared__ float2 tile[];
     __shared__ uint64_t wave_masks[4];
     const int tw = d.tile_w, th = blockDim.x / tw;
-    const int halo = max(R, d.normal_radius);
+    const int halo = max(R * (STR ? d.stride : 1), d.normal_radius);
     const int pitch = tw + 2 * halo;
     stage_region(d, tile, tx * tw - halo, ty * th - halo, pitch, th + 2 * halo);
     const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
@@ -689,9 +716,17 @@ __device__ __forceinline__ void fit_tile_body(const FitDesc& d, int tx, int ty, 
     bool recompute = false;
     if (u < d.width && v < d.height) {
         const float2* centre = tile + (ly + halo) * pitch + (lx + halo);
-        const PixelFit<Real> r = !present(*centre)
-            ? missing_pixel<Real>()
-            : fit_pixel<Real, R, 1, REJ>(d, LdsSource{centre, pitch}, u, v, centre->x, d.residual != nullptr);
+        PixelFit<Real> r;
+        if (!present(*centre)) {
+            r = missing_pixel<Real>();
+        } else if constexpr (STR) {
+            r = fit_pixel<Real, R, 1, REJ, true>(d, LdsSource{centre, pitch},
+                                                 LdsStridedSource{centre, pitch, d.stride}, u, v,
+                                                 centre->x, d.residual != nullptr);
+        } else {
+            const LdsSource src{centre, pitch};
+            r = fit_pixel<Real, R, 1, REJ>(d, src, src, u, v, centre->x, d.residual != nullptr);
+        }
         recompute = mixed && (r.flags & kFlagIll) != 0;
         if (!recompute) store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
     }
@@ -800,9 +835,9 @@ __device__ __forceinline__ void refit_pixel_global(const FitDesc& d, uint32_t ti
     const int u = static_cast<int>(tile % across) * tw + thread % tw;
     const int v = static_cast<int>(tile / across) * th + thread / tw;
     const float Dc = sample_or_missing(d, u, v).x;   // a listed pixel has its depth
-    const PixelFit<double> r = fit_pixel<double, R, kRefitLanes>(
-        d, GlobalSource{static_cast<const char*>(d.depth), d.pitch, d.width, d.height, d.format, u, v},
-        u, v, Dc, d.residual != nullptr, grp);
+    const GlobalSource src{static_cast<const char*>(d.depth), d.pitch, d.width, d.height, d.format, u, v};
+    const PixelFit<double> r = fit_pixel<double, R, kRefitLanes>(d, src, src, u, v, Dc,
+                                                                 d.residual != nullptr, grp);
     if (grp.part == 0) store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
 }
 

@@ -1,6 +1,7 @@
 // fit_frame.h -- per-frame kernels: the FP32 tiled pass, the FP64 pass over every pixel
-// and the FP64 recomputation of listed pixels, templated on the window radius and on the
-// rejection variant; each of fit_frame.hip / fit_frame_reject.hip instantiates one variant.
+// and the FP64 recomputation of listed pixels, templated on the window radius (in samples),
+// the rejection variant (REJ) and a strided fit window (STR); each of fit_frame*.hip
+// instantiates one (REJ, STR) variant.
 #pragma once
 
 #include "fit_device.h"
@@ -9,16 +10,20 @@ namespace qc {
 
 hipError_t launch_frame_reject(const FitDesc& d, const RefitList& list, int cus, hipStream_t st,
                                hipEvent_t* ev);
+hipError_t launch_frame_strided(const FitDesc& d, const RefitList& list, int cus, hipStream_t st,
+                                hipEvent_t* ev);
+hipError_t launch_frame_strided_reject(const FitDesc& d, const RefitList& list, int cus,
+                                       hipStream_t st, hipEvent_t* ev);
 
 namespace {
 
 // FP32 pass over one frame: one 256-lane workgroup per tile (REJ: the rejection variant
 // of Eq. (11)).  Its unrolled rows with FP32 row sums need ~150 registers: 3 waves per
 // SIMD (the pass runs as fast at 2, 3 or 4 waves per SIMD).
-template <int R, bool REJ>
+template <int R, bool REJ, bool STR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))
 void fit_tile_f32(FitDesc d, RefitList list) {
-    fit_tile_body<float, R, REJ>(d, blockIdx.x, blockIdx.y, 0u, list);
+    fit_tile_body<float, R, REJ, STR>(d, blockIdx.x, blockIdx.y, 0u, list);
 }
 
 // FP64 pass over every pixel of one frame: tiles 16 pixels wide, QC_F64_BLOCK lanes.
@@ -28,22 +33,22 @@ void fit_tile_f32(FitDesc d, RefitList list) {
 #ifndef QC_F64_TILE_WAVES
 #define QC_F64_TILE_WAVES 3
 #endif
-template <int R, bool REJ>
+template <int R, bool REJ, bool STR>
 __global__ __launch_bounds__(QC_F64_BLOCK) __attribute__((amdgpu_waves_per_eu(QC_F64_TILE_WAVES)))
 void fit_tile_f64(FitDesc d, RefitList list) {
-    fit_tile_body<double, R, REJ>(d, blockIdx.x, blockIdx.y, 0u, list);
+    fit_tile_body<double, R, REJ, STR>(d, blockIdx.x, blockIdx.y, 0u, list);
 }
 
 // FP64 pass over the listed pixels of one frame; one wave per workgroup, persistent
 // (waves loop until the ranks run out).  For each chunk the wave stages its tile plus halo
 // in LDS, as the FP32 pass did, and fits the chunk's pixels from there.
-template <int R, bool REJ>
+template <int R, bool REJ, bool STR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
 void refit_f64(FitDesc d, RefitList list) {
     extern __shared__ float2 region[];
     const uint32_t ranks = list.counts[0], entries = list.counts[1];
     const int tw = d.tile_w, th = 256 / tw;
-    const int halo = max(R, d.normal_radius);
+    const int halo = max(R * (STR ? d.stride : 1), d.normal_radius);
     const int pitch = tw + 2 * halo;
     const int across = tiles_across(d);
     const LaneGroup<kRefitLanes> grp{static_cast<int>(threadIdx.x % kRefitLanes)};
@@ -59,18 +64,27 @@ void refit_f64(FitDesc d, RefitList list) {
         if (t >= 0) {
             const int lx = t % tw, ly = t / tw;
             const float2* centre = region + (ly + halo) * pitch + (lx + halo);
-            const PixelFit<double> r = fit_pixel<double, R, kRefitLanes, REJ>(
-                d, LdsSource{centre, pitch}, bx + lx, by + ly, centre->x, d.residual != nullptr, grp);
+            PixelFit<double> r;
+            if constexpr (STR) {
+                r = fit_pixel<double, R, kRefitLanes, REJ, true>(
+                    d, LdsSource{centre, pitch}, LdsStridedSource{centre, pitch, d.stride}, bx + lx,
+                    by + ly, centre->x, d.residual != nullptr, grp);
+            } else {
+                const LdsSource src{centre, pitch};
+                r = fit_pixel<double, R, kRefitLanes, REJ>(d, src, src, bx + lx, by + ly, centre->x,
+                                                           d.residual != nullptr, grp);
+            }
             if (grp.part == 0) store_pixel(d, static_cast<int64_t>(by + ly) * d.width + bx + lx, r);
         }
         __syncthreads();   // the next chunk re-stages the region
     }
 }
 
-template <int R, bool REJ>
+template <int R, bool REJ, bool STR>
 hipError_t launch_variant(const FitDesc& d, const RefitList& list, int cus, hipStream_t st,
                           hipEvent_t* ev) {
-    const int halo = R > d.normal_radius ? R : d.normal_radius;
+    const int reach = R * (STR ? d.stride : 1);   // pixels from the centre to the last sample
+    const int halo = reach > d.normal_radius ? reach : d.normal_radius;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if (d.precision == 2) {
@@ -78,7 +92,7 @@ hipError_t launch_variant(const FitDesc& d, const RefitList& list, int cus, hipS
         d64.tile_w = kTileW;
         constexpr int th64 = QC_F64_BLOCK / kTileW;
         dim3 grid((d.width + kTileW - 1) / kTileW, (d.height + th64 - 1) / th64);
-        hipLaunchKernelGGL((fit_tile_f64<R, REJ>), grid, dim3(QC_F64_BLOCK), lds_bytes(kTileW, th64, halo),
+        hipLaunchKernelGGL((fit_tile_f64<R, REJ, STR>), grid, dim3(QC_F64_BLOCK), lds_bytes(kTileW, th64, halo),
                            st, d64, list);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
@@ -88,31 +102,33 @@ hipError_t launch_variant(const FitDesc& d, const RefitList& list, int cus, hipS
     const int tw = d.tile_w, th = 256 / tw;
     const size_t lds = lds_bytes(tw, th, halo);
     dim3 grid((d.width + tw - 1) / tw, (d.height + th - 1) / th);
-    hipLaunchKernelGGL((fit_tile_f32<R, REJ>), grid, dim3(256), lds, st, d, list);
+    hipLaunchKernelGGL((fit_tile_f32<R, REJ, STR>), grid, dim3(256), lds, st, d, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
     if (d.precision == 0) {
-        hipLaunchKernelGGL((refit_f64<R, REJ>), dim3(16 * cus), dim3(64), lds, st, d, list);
+        hipLaunchKernelGGL((refit_f64<R, REJ, STR>), dim3(16 * cus), dim3(64), lds, st, d, list);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
     return hipSuccess;
 }
 
-template <bool REJ, int... Rs>
+template <bool REJ, bool STR, int... Rs>
 hipError_t dispatch_radius(int r, const FitDesc& d, const RefitList& list, int cus,
                            hipStream_t st, hipEvent_t* ev, std::integer_sequence<int, Rs...>) {
     hipError_t e = hipErrorInvalidValue;
-    (void)((r == Rs + 1 ? (e = launch_variant<Rs + 1, REJ>(d, list, cus, st, ev), true) : false) || ...);
+    (void)((r == Rs + 1 ? (e = launch_variant<Rs + 1, REJ, STR>(d, list, cus, st, ev), true) : false) || ...);
     return e;
 }
 
-// The per-frame kernels for every window radius, with (REJ) or without rejection.
-template <bool REJ>
+// The per-frame kernels for every window size: with (REJ) or without rejection, the window
+// dense or (STR) sampled every d.stride pixels, r / stride samples either side.
+template <bool REJ, bool STR>
 hipError_t launch_frame(const FitDesc& d, const RefitList& list, int cus, hipStream_t st,
                         hipEvent_t* ev) {
-    return dispatch_radius<REJ>(d.radius, d, list, cus, st, ev,
-                                std::make_integer_sequence<int, kMaxRadius>{});
+    const int samples = STR ? d.radius / d.stride : d.radius;
+    return dispatch_radius<REJ, STR>(samples, d, list, cus, st, ev,
+                                     std::make_integer_sequence<int, kMaxRadius>{});
 }
 
 }  // namespace

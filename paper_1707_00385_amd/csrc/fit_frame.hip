@@ -34,8 +34,11 @@ hipError_t launch_fit(const FitDesc& d, const RefitList& list, int cus, hipStrea
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (d.stride > 1)
+        return d.reject ? launch_frame_strided_reject(d, list, cus, stream, events)
+                        : launch_frame_strided(d, list, cus, stream, events);
     return d.reject ? launch_frame_reject(d, list, cus, stream, events)
-                    : launch_frame<false>(d, list, cus, stream, events);
+                    : launch_frame<false, false>(d, list, cus, stream, events);
 }
 
 }  // namespace qc

@@ -5,7 +5,7 @@ namespace qc {
 
 hipError_t launch_frame_reject(const FitDesc& d, const RefitList& list, int cus, hipStream_t st,
                                hipEvent_t* ev) {
-    return launch_frame<true>(d, list, cus, st, ev);
+    return launch_frame<true, false>(d, list, cus, st, ev);
 }
 
 }  // namespace qc

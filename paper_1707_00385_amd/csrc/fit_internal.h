@@ -19,6 +19,7 @@ struct FitDesc {
     float cond_max, step_max;
     int32_t precision;       // qc_precision
     int32_t reject;          // 1: rejection variant of Eq. (11) (per-frame kernels only)
+    int32_t stride;          // fit window sampled every `stride` pixels (per-frame kernels only)
     int32_t tile_w;          // FP32 pass tile width: 8, 16, 32 or 64 (256 / tile_w rows)
     float* k1;
     float* k2;

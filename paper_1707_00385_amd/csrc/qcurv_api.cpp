@@ -92,6 +92,7 @@ qc_status check_params(const qc_params* p) {
     if (std::isnan(p->cond_max) || std::isnan(p->step_max)) return QC_ERR_INVALID_ARG;
     if (p->tile_width != 0 && !qc::valid_tile_width(p->tile_width)) return QC_ERR_INVALID_ARG;
     if (p->reject != 0 && p->reject != 1) return QC_ERR_INVALID_ARG;
+    if (p->stride < 1 || p->stride > p->radius) return QC_ERR_INVALID_ARG;
     return QC_OK;
 }
 
@@ -145,6 +146,7 @@ qc::FitDesc make_desc(const qc_frame* frame, const qc_params* params, const qc_o
     d.step_max = params->step_max;
     d.precision = params->precision;
     d.reject = params->reject;
+    d.stride = params->stride;
     d.tile_w = tile_w;
     d.k1 = out->k1;
     d.k2 = out->k2;
@@ -253,6 +255,7 @@ void qc_params_default(qc_params* p) {
     p->cond_max = 30.f;
     p->step_max = 1e-1f;
     p->tile_width = 0;
+    p->stride = 1;
 }
 
 qc_status qc_create(qc_context** out, int device) {
@@ -333,14 +336,14 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
     if (n == 0) return QC_OK;
     qc_status st;
     const int32_t prec = items[0].params.precision;
-    bool any_reject = false;
+    bool per_frame = false;
     for (int32_t i = 0; i < n; ++i) {
         const qc_batch_item& it = items[i];
         if ((st = check_frame(&it.frame)) != QC_OK) return st;
         if ((st = check_params(&it.params)) != QC_OK) return st;
         if (!it.out.k1 || !it.out.k2) return QC_ERR_INVALID_ARG;
         if (it.params.precision != prec) return QC_ERR_INVALID_ARG;
-        any_reject |= it.params.reject != 0;
+        per_frame |= it.params.reject != 0 || it.params.stride != 1;
     }
     if (prec == QC_PREC_FP64) return QC_ERR_UNSUPPORTED;
     hipError_t e;
@@ -375,10 +378,11 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
     std::memcpy(s.host->first_tile, first.data(), sizeof(uint32_t) * (n + 1));
     s.host->header[0] = static_cast<uint32_t>(n);
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    if (any_reject) {
-        // The batched kernels carry only the default weights of Eq. (11): a batch holding
-        // rejection frames runs as per-frame launches, in order on the stream, on the
-        // slot's own list (so that two batches in flight on two streams share none).
+    if (per_frame) {
+        // The batched kernels carry only the default weights of Eq. (11) and dense
+        // windows: a batch holding rejection or strided frames runs as per-frame launches,
+        // in order on the stream, on the slot's own list (so that two batches in flight on
+        // two streams share none).
         const qc::RefitList list = qc::refit_list(s.list, s.capacity, s.counts);
         for (int32_t j = 0; j < n; ++j)
             if ((e = qc::launch_fit(descs[j], list, ctx->cus, hs)) != hipSuccess) return hip_fail(ctx, e);

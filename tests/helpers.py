@@ -34,7 +34,7 @@ PERTURBATION = 2.0 ** -44
 
 
 def oracle_fit(depth, fmt, cam, radius, iterations, k, normal_radius=3, scale=1e-3, pixels=None,
-               perturb=0, reject=False):
+               perturb=0, reject=False, stride=1):
     """The oracle on the GPU's exact input.  perturb=s (s > 0) multiplies every depth by
     1 +- PERTURBATION with signs drawn from seed s: a rounding-level change of the input
     that shows which pixels' results are not determined by the input at the tolerance."""
@@ -47,16 +47,16 @@ def oracle_fit(depth, fmt, cam, radius, iterations, k, normal_radius=3, scale=1e
     kk = float(np.float32(k))
     if pixels is None:
         return oracle.fit_image(d, *K, radius=radius, iterations=iterations, k=kk,
-                                normal_radius=normal_radius, reject=reject)
+                                normal_radius=normal_radius, reject=reject, stride=stride)
     return oracle.fit_pixels(d, pixels, *K, radius=radius, iterations=iterations, k=kk,
-                             normal_radius=normal_radius, reject=reject)
+                             normal_radius=normal_radius, reject=reject, stride=stride)
 
 
 def oracle_pair(depth, fmt, cam, radius, iterations, k, normal_radius=3, scale=1e-3, pixels=None,
-                reject=False):
+                reject=False, stride=1):
     """The oracle and its sensitivity probe: the probe result holds, per pixel, the
     perturbed run (of two, differently seeded) that is farthest from the oracle."""
-    kw = dict(normal_radius=normal_radius, scale=scale, pixels=pixels, reject=reject)
+    kw = dict(normal_radius=normal_radius, scale=scale, pixels=pixels, reject=reject, stride=stride)
     o = oracle_fit(depth, fmt, cam, radius, iterations, k, **kw)
     a = oracle_fit(depth, fmt, cam, radius, iterations, k, perturb=1, **kw)
     b = oracle_fit(depth, fmt, cam, radius, iterations, k, perturb=2, **kw)

@@ -3,6 +3,7 @@ No compute call is made here (no GPU needed)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -34,7 +35,7 @@ def test_defaults_and_status_strings():
     lib.qc_params_default(ctypes.byref(p))
     assert (p.radius, p.normal_radius, p.iterations) == (7, 3, 5)
     assert p.k == pytest.approx(1e-5) and p.depth_scale == pytest.approx(1e-3)
-    assert p.precision == _lib.QC_PREC_MIXED and p.reject == 0
+    assert p.precision == _lib.QC_PREC_MIXED and p.reject == 0 and p.stride == 1
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.qc_status_string(code)
     assert lib.qc_status_string(12345) == b"unknown status"
@@ -47,3 +48,36 @@ def test_null_arguments_rejected_without_a_device():
     assert lib.qc_destroy(None) == 0
     assert lib.qc_last_hip_error(None) == 0
     assert lib.qc_last_refit_count(None, None) == -1
+
+
+# struct name in the header -> ctypes class in the binding
+_STRUCTS = {"qc_intrinsics": "Intrinsics", "qc_params": "Params", "qc_frame": "Frame",
+            "qc_output": "Output", "qc_batch_item": "BatchItem", "qc_server_config": "ServerConfig",
+            "qc_request": "Request", "qc_completion": "Completion", "qc_server_stats": "ServerStats",
+            "qc_timing": "Timing"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every struct the binding marshals has the header's size and field offsets (a C
+    program compiled against include/qcurv.h prints them)."""
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "qcurv.h"', 'int main(void) {']
+    for c_name, py_name in _STRUCTS.items():
+        cls = getattr(_lib, py_name)
+        lines.append(f'printf("{c_name} size %zu\\n", sizeof({c_name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{c_name} {field} %zu\\n", offsetof({c_name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        struct, field, value = line.split()
+        got[(struct, field)] = int(value)
+    for c_name, py_name in _STRUCTS.items():
+        cls = getattr(_lib, py_name)
+        assert got[(c_name, "size")] == ctypes.sizeof(cls), c_name
+        for field, _ in cls._fields_:
+            assert got[(c_name, field)] == getattr(cls, field).offset, (c_name, field)

@@ -113,6 +113,22 @@ def test_batch_with_rejection_equals_per_frame_calls(ctx):
         _equal({k: v.cpu().numpy() for k, v in o.items()}, single, f"frame {i}")
 
 
+def test_batch_with_strided_items_equals_per_frame_calls(ctx):
+    """Batches holding strided items run as per-frame launches: same outputs."""
+    import torch
+    jobs = _jobs()[:4]
+    bj = _batch_jobs(jobs)
+    for i, (_, _, p, _) in enumerate(bj):
+        if i % 2 == 0 and p.radius >= 2:
+            p.stride = 2
+    log(f"[case] batch of {len(bj)} frames, some strided")
+    outs = ctx.fit_batch(bj)
+    torch.cuda.synchronize()
+    for i, ((t, K, p, _), o) in enumerate(zip(bj, outs)):
+        single = _run_single(ctx, t, jobs[i][1], p)
+        _equal({k: v.cpu().numpy() for k, v in o.items()}, single, f"frame {i}")
+
+
 def test_batch_graph_replays_match_eager(ctx):
     """The batch runs from a captured graph; replay it several times with the program's
     own GPU work and synchronisations in between, and check every replay."""

@@ -26,13 +26,13 @@ def ctx():
 
 
 def _run(ctx, name, depth, fmt, cam, radius, iterations, tol, precision="mixed", k=1e-5,
-         normal_radius=3, reject=False, **kw):
+         normal_radius=3, reject=False, stride=1, **kw):
     log(f"[case] {name} fmt={fmt} {cam.width}x{cam.height} r={radius} T={iterations} {precision}"
-        f"{' reject' if reject else ''}")
+        f"{' reject' if reject else ''}{f' stride={stride}' if stride > 1 else ''}")
     g = gpu_fit(ctx, depth, fmt, cam, radius=radius, iterations=iterations, k=k,
-                normal_radius=normal_radius, precision=precision, reject=int(reject))
+                normal_radius=normal_radius, precision=precision, reject=int(reject), stride=stride)
     o, oa = oracle_pair(depth, fmt, cam, radius, iterations, k, normal_radius=normal_radius,
-                        reject=reject)
+                        reject=reject, stride=stride)
     return compare(g, o, tol, name, o_alt=oa, **kw), g, o
 
 
@@ -137,3 +137,36 @@ def test_reject_changes_results_near_outliers(ctx):
     both = ((a["flags"] & 1) == 1) & ((b["flags"] & 1) == 1)
     diff = np.abs(a["k1"] - b["k1"])[both]
     assert (diff > 0).mean() > 0.5
+
+
+# ---- strided ("sparsely sampled") fit window: offsets that are multiples of the stride ----
+
+# (7, 7) is the sparsest window: 3x3 samples for six parameters.  Such a fit is barely
+# determined, and a few percent of its pixels move under the rounding-level probe.
+@pytest.mark.parametrize("radius,stride,nonunique", [(6, 2, 0.01), (18, 3, 0.01), (7, 7, 0.05)])
+def test_strided_window_small(ctx, radius, stride, nonunique):
+    cam = scenes.Camera(100, 75, 90.0, 90.0, 49.5, 37.0)
+    sc = scenes.cluttered_scene(cam, seed_frame=14, config_index=8)
+    _run(ctx, f"stride clutter100x75 r={radius} s={stride}", sc.depth_u16(), "u16", cam, radius, 5,
+         1e-3, stride=stride, residual_tol=1e-2, max_nonunique=nonunique)
+
+
+def test_strided_paper_patch_vga(ctx):
+    """The paper's largest patch, 37x37, sampled every third pixel (13x13 samples), on a
+    full headline-like frame."""
+    sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=3, config_index=1)
+    st, g, _ = _run(ctx, "stride vga 37x37/3", sc.depth_u16(), "u16", sc.camera, 18, 5, 1e-3, stride=3)
+    log("  refit fraction", st["refits"] / st["pixels"])
+
+
+def test_strided_fp64_mode_tight(ctx):
+    sc = scenes.cluttered_scene(scenes.Camera(96, 72, 80.0, 80.0, 47.5, 35.5), seed_frame=15,
+                                config_index=7)
+    _run(ctx, "stride fp64", sc.depth_u16(), "u16", sc.camera, 10, 5, 2e-7, precision="fp64",
+         stride=2, normal_tol=2e-7, residual_tol=2e-7)
+
+
+def test_strided_with_rejection(ctx):
+    cam = scenes.Camera(100, 75, 90.0, 90.0, 49.5, 37.0)
+    sc = scenes.cluttered_scene(cam, seed_frame=16, config_index=8)
+    _run(ctx, "stride+reject", sc.depth_u16(), "u16", cam, 8, 5, 1e-3, stride=2, reject=True)
