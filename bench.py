@@ -272,6 +272,45 @@ def measure_rejection(ctx, dev, K, precision: str, steps: int = 100) -> dict:
             "workload": "headline frames, reject=1 (R = 2 x unweighted MSE of the window)"}
 
 
+# The paper's timing table (Section 4, one Tesla K40c; iterations and k not given, 37x37
+# "sparsely sampled" with the stride not given): ms per frame, quoted as context.
+PAPER_GRID_MS = {(640, 480): (10.2, 16.1, 19.3), (512, 424): (6.7, 12.2, 13.2),
+                 (320, 240): (2.5, 4.5, 5.0)}
+PAPER_PATCHES = ((4, 1, "9x9"), (10, 1, "21x21"), (18, 3, "37x37 every 3rd pixel (13x13 samples)"))
+
+
+def measure_paper_grid(ctx, steps: int = 50) -> list:
+    """The paper's timing grid on this GPU: three image sizes x three patches (T = 5,
+    MIXED), one seeded cluttered u16 frame per size, per-frame launches."""
+    import torch
+    from paper_1707_00385_amd import scenes
+    from paper_1707_00385_amd.api import make_outputs, make_params, upload_depth
+    cams = {(640, 480): scenes.CAM_VGA, (512, 424): scenes.CAM_TOF,
+            (320, 240): scenes.Camera(320, 240, 262.5, 262.5, 159.5, 119.5)}
+    rows = []
+    for (w, h), cam in cams.items():
+        sc = scenes.cluttered_scene(cam, seed_frame=0, config_index=10)
+        t = upload_depth(sc.depth_u16(), "u16")
+        K = (cam.fx, cam.fy, cam.cx, cam.cy)
+        out = make_outputs(h, w, t.device, flags=False)
+        for j, (r, stride, label) in enumerate(PAPER_PATCHES):
+            p = make_params(radius=r, iterations=ITERS, k=K_ROBUST, stride=stride)
+            for _ in range(5):
+                ctx.fit(t, K, params=p, out=out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.fit(t, K, params=p, out=out)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / steps
+            ctx.fit(t, K, params=p, out=out)
+            rows.append({"image": f"{w}x{h}", "patch": label, "radius": r, "stride": stride,
+                         "ms_per_frame": round(ms, 4), "pixels_per_s": round(w * h / ms * 1e3, 1),
+                         "refit_fraction": round(ctx.last_refit_count() / (w * h), 4),
+                         "paper_k40c_ms": PAPER_GRID_MS[(w, h)][j]})
+    return rows
+
+
 def copy_calibration(nbytes: int) -> int:
     """Ten device-to-device copies of a known size: the HBM read/write counters of these
     dispatches give the scale factor between counter readings and bytes moved."""
@@ -296,6 +335,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-reject", action="store_true")
+    ap.add_argument("--no-paper-grid", action="store_true")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 10 plain device copies of BYTES bytes (calibrates the "
@@ -396,6 +436,8 @@ def main() -> int:
     }
     if not args.no_reject:
         result["rejection_variant"] = measure_rejection(ctx, dev, K, args.precision)
+    if not args.no_paper_grid and args.precision == "mixed":
+        result["paper_timing_grid"] = measure_paper_grid(ctx)
     if not args.no_batched and args.precision != "fp64":
         result["batched_form"] = measure_batched(ctx)
     if not args.no_served and args.precision != "fp64":

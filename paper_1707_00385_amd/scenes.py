@@ -198,6 +198,63 @@ def _cylinder(rays, centre, axis, radius, length):
     return t, k1, k2, n, use_cap & np.isfinite(t)
 
 
+def _torus(rays, centre, rot, R, r):
+    """Torus with major radius R (centre circle) and minor radius r (tube) around the
+    axis rot[:, 2] through `centre`.  The ray/torus intersection is the smallest positive
+    real root of a quartic, found from the eigenvalues of its companion matrix and
+    polished by Newton steps.  Principal curvatures w.r.t. the outward normal: -1/r across
+    the tube and -cos(v)/(R + r cos(v)) along it, v the tube angle (0 on the outer
+    equator)."""
+    dx, dy, dz = rays
+    shape = dx.shape
+    c = np.asarray(centre, dtype=np.float64)
+    Q = np.asarray(rot, dtype=np.float64)
+    d = np.stack([dx.ravel(), dy.ravel(), dz.ravel()], axis=1) @ Q      # ray directions, torus frame
+    o = -(Q.T @ c)                                                        # camera origin, torus frame
+    t = np.full(d.shape[0], np.inf)
+    # rays passing within R + r of the centre can hit
+    dn = d / np.linalg.norm(d, axis=1, keepdims=True)
+    closest = np.linalg.norm(o[None, :] - (dn @ o)[:, None] * dn, axis=1)
+    cand = np.nonzero(closest < R + r)[0]
+    if cand.size:
+        dd = d[cand]
+        a = np.sum(dd * dd, axis=1)
+        B = 2.0 * (dd @ o)
+        A = float(o @ o) + R * R - r * r
+        rxy = dd[:, 0] ** 2 + dd[:, 1] ** 2
+        oxy = dd[:, 0] * o[0] + dd[:, 1] * o[1]
+        coef = np.stack([a * a, 2 * a * B, B * B + 2 * a * A - 4 * R * R * rxy,
+                         2 * A * B - 8 * R * R * oxy,
+                         np.full(a.shape, A * A - 4 * R * R * (o[0] ** 2 + o[1] ** 2))], axis=1)
+        mon = coef[:, 1:] / coef[:, :1]
+        comp = np.zeros((cand.size, 4, 4))
+        comp[:, 0, :] = -mon
+        comp[:, 1, 0] = comp[:, 2, 1] = comp[:, 3, 2] = 1.0
+        roots = np.linalg.eigvals(comp)
+        real = np.abs(roots.imag) <= 1e-7 * np.maximum(1.0, np.abs(roots.real))
+        tr = np.where(real & (roots.real > 0), roots.real, np.inf)
+        tt = tr.min(axis=1)
+        ok = np.isfinite(tt)
+        for _ in range(4):   # Newton on the quartic
+            p4 = (((coef[:, 0] * tt + coef[:, 1]) * tt + coef[:, 2]) * tt + coef[:, 3]) * tt + coef[:, 4]
+            dp = ((4 * coef[:, 0] * tt + 3 * coef[:, 1]) * tt + 2 * coef[:, 2]) * tt + coef[:, 3]
+            step = np.where(ok & (dp != 0), p4 / np.where(dp != 0, dp, 1.0), 0.0)
+            tt = np.where(ok, tt - step, tt)
+        t[cand] = tt
+    p = o[None, :] + t[:, None] * d
+    rho = np.sqrt(p[:, 0] ** 2 + p[:, 1] ** 2)
+    ring = np.stack([p[:, 0] / rho * R, p[:, 1] / rho * R, np.zeros_like(rho)], axis=1)
+    n_local = (p - ring) / np.linalg.norm(p - ring, axis=1, keepdims=True)
+    cosv = (rho - R) / r
+    n = (n_local @ Q.T).T.reshape(3, *shape)
+    ka = np.full(rho.shape, -1.0 / r)
+    kb = -cosv / (R + r * cosv)
+    k1 = np.maximum(ka, kb).reshape(shape)
+    k2 = np.minimum(ka, kb).reshape(shape)
+    k1, k2, n = _orient(k1, k2, n, rays)
+    return t.reshape(shape), k1, k2, n, np.zeros(shape, dtype=bool)
+
+
 def monge_curvatures(fx, fy, fxx, fxy, fyy):
     """Principal curvatures of z = f(x, y) w.r.t. the normal (-f_x, -f_y, 1)/sqrt(W)."""
     Wm = 1.0 + fx * fx + fy * fy
@@ -417,6 +474,29 @@ def single_shape_scene(kind: str, camera: Camera, distance: float, radius: float
         raise ValueError(kind)
     d, k1, k2, n, sid = _composite(camera, [fn])
     return Scene(camera, d.copy(), d, k1, k2, n, sid, dict(kind=kind, radius=radius))
+
+
+def torus_scene(camera: Camera, distance: float, R: float = 0.10, r: float = 0.03,
+                rot: Optional[np.ndarray] = None, noise_sigma: float = 0.0, seed_frame: int = 0,
+                background: Optional[float] = None) -> Scene:
+    """A torus (Table 1's synthetic torus: R = 100 mm, r = 30 mm) centred on the optical
+    axis at `distance`, axis tilted by `rot` (default 60 degrees about x, so both the
+    outer and the inner, saddle-shaped side face the camera); optional constant-sigma
+    noise on Z and a fronto-parallel background plane."""
+    if rot is None:
+        a = np.deg2rad(60.0)
+        rot = np.array([[1.0, 0.0, 0.0], [0.0, np.cos(a), -np.sin(a)], [0.0, np.sin(a), np.cos(a)]])
+    shapes = [lambda rays: _torus(rays, (0.0, 0.0, distance), rot, R, r)]
+    if background is not None:
+        shapes.append(lambda rays: _plane(rays, (0.0, 0.0, background), (0.0, 0.0, -1.0)))
+    d, k1, k2, n, sid = _composite(camera, shapes)
+    rng = rng_for(11, seed_frame)
+    depth = d.copy()
+    if noise_sigma > 0:
+        depth = np.where(d > 0, d + rng.standard_normal(d.shape) * noise_sigma, 0.0)
+        depth = np.where(depth > 0, depth, 0.0)
+    return Scene(camera, depth, d, k1, k2, n, sid,
+                 dict(kind="torus", R=R, r=r, distance=distance, noise_sigma=noise_sigma))
 
 
 def saddle_scene(camera: Camera, distance: float, R: float, rot: np.ndarray,

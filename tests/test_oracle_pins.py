@@ -484,3 +484,53 @@ def test_stride_one_is_the_dense_window():
     b = oracle.fit_image(sc.depth_m, *_cam(sc), radius=3, iterations=3, k=1e-5, stride=1)
     for key in ("k1", "k2", "normal", "residual", "flags"):
         assert np.array_equal(a[key], b[key], equal_nan=True)
+
+
+# ---- torus (Table 1's third synthetic shape): k = 1/r across the tube and
+#      cos(v)/(R + r cos(v)) along it, v the tube angle ----
+
+def test_torus_generator_is_on_the_surface():
+    """The ray-cast torus: hit points satisfy the implicit equation, normals are unit and
+    face away from the camera, and the closed-form curvatures span the expected ranges."""
+    cam = scenes.Camera(200, 160, 400.0, 400.0, 99.5, 79.5)
+    sc = scenes.torus_scene(cam, 0.6)
+    hit = sc.depth_clean_m > 0
+    assert hit.sum() > 2000
+    dx, dy, dz = cam.rays()
+    Z = sc.depth_clean_m
+    P = np.stack([dx * Z, dy * Z, Z], -1)[hit]
+    a = np.deg2rad(60.0)
+    rot = np.array([[1, 0, 0], [0, np.cos(a), -np.sin(a)], [0, np.sin(a), np.cos(a)]])
+    q = (P - np.array([0, 0, 0.6])) @ rot
+    R, r = 0.10, 0.03
+    f = (np.sum(q * q, 1) + R * R - r * r) ** 2 - 4 * R * R * (q[:, 0] ** 2 + q[:, 1] ** 2)
+    assert np.abs(f).max() < 1e-14
+    n = sc.normal_true[hit]
+    assert np.abs(np.linalg.norm(n, axis=1) - 1).max() < 1e-12
+    ray = np.stack([dx, dy, dz], -1)[hit]
+    assert (np.sum(n * ray, 1) > 0).all()
+    np.testing.assert_allclose(sc.k1_true[hit], 1 / r, rtol=1e-12)
+    assert sc.k2_true[hit].min() < -1 / (R - r) + 0.5 and sc.k2_true[hit].max() > 1 / (R + r) - 0.5
+
+
+def test_torus_oracle_matches_closed_form():
+    """Noiseless torus, 7x7 window: the fit reproduces both closed-form curvatures, on the
+    convex outer side and the saddle-shaped inner side, within the truncation bias of a
+    parabola over a window of surface half-extent h / cos(theta)."""
+    f, rad, dist, r_t = 1050.0, 3, 0.6, 0.03
+    cam = scenes.Camera(240, 200, f, f, 119.5, 99.5)
+    sc = scenes.torus_scene(cam, dist)
+    m = sc.eval_mask(rad)
+    dx, dy, dz = cam.rays()
+    ray = np.stack([dx, dy, dz], -1)
+    ray /= np.linalg.norm(ray, axis=-1, keepdims=True)
+    cos_t = np.abs(np.sum(ray * sc.normal_true, -1))
+    m &= cos_t >= 0.5
+    o = oracle.fit_image(sc.depth_m, *_cam(sc), radius=rad, iterations=10, k=1e-5)
+    h = rad * sc.depth_m / f
+    with np.errstate(divide="ignore", invalid="ignore"):   # cos_t = 0 off the torus
+        bound = 3 * (h / (r_t * cos_t)) ** 2 / r_t
+    e = np.maximum(np.abs(o["k1"] - sc.k1_true), np.abs(o["k2"] - sc.k2_true))
+    assert m.sum() > 10000
+    assert (sc.k2_true[m] < 0).sum() > 1000 and (sc.k2_true[m] > 0).sum() > 1000
+    assert (e[m] <= bound[m]).all()
