@@ -311,6 +311,112 @@ def measure_paper_grid(ctx, steps: int = 50) -> list:
     return rows
 
 
+def _fit_gpu(ctx, depth_m, cam, radius, stride=1):
+    import torch
+    from paper_1707_00385_amd.api import upload_depth
+    t = upload_depth(depth_m.astype(np.float32), "f32")
+    out = ctx.fit(t, (cam.fx, cam.fy, cam.cx, cam.cy), radius=radius, iterations=ITERS,
+                  k=K_ROBUST, stride=stride, normal=True)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _rms(x):
+    return float(np.sqrt(np.mean(np.square(x)))) if x.size else float("nan")
+
+
+def pca_normals(depth_m: np.ndarray, cam, r: int) -> np.ndarray:
+    """Normal of the least-variance direction of the back-projected points in each
+    (2r+1)^2 window (the usual PCA normal; missing depth skipped), facing away from the
+    camera.  A comparison baseline, computed on the host."""
+    dx, dy, _ = cam.rays()
+    valid = depth_m > 0
+    P = np.stack([dx * depth_m, dy * depth_m, depth_m], -1) * valid[..., None]
+    def box(a):
+        pad = np.pad(a, [(r + 1, r)] + [(r + 1, r)] + [(0, 0)] * (a.ndim - 2))
+        c = pad.cumsum(0).cumsum(1)
+        n = 2 * r + 1
+        return c[n:, n:] - c[:-n, n:] - c[n:, :-n] + c[:-n, :-n]
+    N = box(valid.astype(np.float64)[..., None])[..., 0]
+    S1 = box(P)
+    S2 = box(np.einsum("hwi,hwj->hwij", P, P).reshape(*P.shape[:2], 9)).reshape(*P.shape[:2], 3, 3)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mean = S1 / N[..., None]
+        cov = S2 / N[..., None, None] - np.einsum("hwi,hwj->hwij", mean, mean)
+    cov = np.where(np.isfinite(cov), cov, 0.0)
+    _, vec = np.linalg.eigh(cov)
+    n = vec[..., :, 0]
+    ray = np.stack([dx, dy, np.ones_like(dx)], -1)
+    return np.where((np.sum(n * ray, -1) < 0)[..., None], -n, n)
+
+
+def _angle_deg(a, b):
+    c = np.clip(np.sum(a * b, -1) / (np.linalg.norm(a, axis=-1) * np.linalg.norm(b, axis=-1)), -1, 1)
+    return np.degrees(np.arccos(c))
+
+
+def measure_accuracy(ctx) -> dict:
+    """Error against the closed-form truth of the synthetic shapes (Section 4): the
+    100 mm sphere under increasing noise, refined vs PCA normals on the headline frame,
+    and the Table 1 torus (R = 100 mm, r = 30 mm).  MIXED precision, T = 5, k = 1e-5;
+    dense 15x15 windows and the 37x37 patch sampled every third pixel."""
+    from paper_1707_00385_amd import scenes
+    out = {}
+    # (1) sphere r = 0.1 m at 0.6 m, constant-sigma noise on Z
+    cam = scenes.CAM_VGA
+    sph = scenes.single_shape_scene("sphere", cam, 0.6, 0.1)
+    rng = np.random.default_rng([1707_00385, 20, 0])
+    hit = sph.depth_clean_m > 0
+    rows = []
+    for sigma_mm in (0.0, 0.25, 0.5, 1.0, 2.0):
+        d = np.where(hit, sph.depth_clean_m + rng.standard_normal(hit.shape) * sigma_mm * 1e-3, 0.0)
+        for radius, stride in ((7, 1), (18, 3)):
+            g = _fit_gpu(ctx, d, cam, radius, stride)
+            m = sph.eval_mask(radius) & ((g["flags"] & 1) == 1)
+            err = np.concatenate([g["k1"][m] - 10.0, g["k2"][m] - 10.0])
+            rows.append({"sigma_mm": sigma_mm, "window": f"{2 * radius + 1}x{2 * radius + 1}/{stride}",
+                         "pixels": int(m.sum()), "rms_err_per_m": round(_rms(err), 5),
+                         "mean_k_per_m": round(float(np.mean(np.concatenate([g["k1"][m], g["k2"][m]]))), 5)})
+    out["sphere_100mm_noise_sweep"] = {"truth_per_m": 10.0, "distance_m": 0.6, "rows": rows,
+                                       "paper_rms_per_m": 0.037}
+    # (2) normals on the headline frame: refined (Section 3.2.4) vs initial vs PCA
+    sc = scenes.cluttered_scene(cam, seed_frame=0, config_index=1)
+    d = sc.depth_u16().astype(np.float64) * 1e-3
+    g = _fit_gpu(ctx, d, cam, RADIUS)
+    g0 = None
+    import torch
+    from paper_1707_00385_amd.api import upload_depth
+    t = upload_depth(d.astype(np.float32), "f32")
+    o0 = ctx.fit(t, (cam.fx, cam.fy, cam.cx, cam.cy), radius=RADIUS, iterations=0, normal=True)
+    torch.cuda.synchronize()
+    g0 = o0["normal"].cpu().numpy()
+    m = sc.eval_mask(RADIUS) & ((g["flags"] & 1) == 1)
+    nt = sc.normal_true
+    ang = {"refined_15x15": _angle_deg(g["normal"], nt)[m],
+           "initial_7x7_regression": _angle_deg(g0, nt)[m],
+           "pca_7x7": _angle_deg(pca_normals(d, cam, 3), nt)[m],
+           "pca_15x15": _angle_deg(pca_normals(d, cam, RADIUS), nt)[m]}
+    out["normal_angle_deg_headline"] = {
+        "pixels": int(m.sum()),
+        **{k: {"median": round(float(np.median(v)), 4), "rms": round(_rms(v), 4)} for k, v in ang.items()}}
+    # (3) torus R = 0.1 m, r = 0.03 m at 0.6 m, pixels seen within 60 degrees of head-on
+    tor_rows = []
+    for sigma_mm in (0.0, 1.0):
+        tor = scenes.torus_scene(cam, 0.6, noise_sigma=sigma_mm * 1e-3)
+        dx, dy, dz = cam.rays()
+        ray = np.stack([dx, dy, dz], -1)
+        ray /= np.linalg.norm(ray, axis=-1, keepdims=True)
+        cos_t = np.abs(np.sum(ray * tor.normal_true, -1))
+        for radius, stride in ((7, 1), (18, 3)):
+            g = _fit_gpu(ctx, tor.depth_m, cam, radius, stride)
+            m = tor.eval_mask(radius) & (cos_t >= 0.5) & ((g["flags"] & 1) == 1)
+            err = np.concatenate([g["k1"][m] - tor.k1_true[m], g["k2"][m] - tor.k2_true[m]])
+            tor_rows.append({"sigma_mm": sigma_mm, "window": f"{2 * radius + 1}x{2 * radius + 1}/{stride}",
+                             "pixels": int(m.sum()), "rms_err_per_m": round(_rms(err), 4)})
+    out["torus_100_30mm"] = {"rows": tor_rows, "paper_rms_per_m": 0.63}
+    return out
+
+
 def copy_calibration(nbytes: int) -> int:
     """Ten device-to-device copies of a known size: the HBM read/write counters of these
     dispatches give the scale factor between counter readings and bytes moved."""
@@ -336,6 +442,7 @@ def main() -> int:
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-reject", action="store_true")
     ap.add_argument("--no-paper-grid", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 10 plain device copies of BYTES bytes (calibrates the "
@@ -438,6 +545,8 @@ def main() -> int:
         result["rejection_variant"] = measure_rejection(ctx, dev, K, args.precision)
     if not args.no_paper_grid and args.precision == "mixed":
         result["paper_timing_grid"] = measure_paper_grid(ctx)
+    if not args.no_accuracy and args.precision == "mixed":
+        result["accuracy"] = measure_accuracy(ctx)
     if not args.no_batched and args.precision != "fp64":
         result["batched_form"] = measure_batched(ctx)
     if not args.no_served and args.precision != "fp64":
