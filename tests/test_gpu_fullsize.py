@@ -1,0 +1,157 @@
+"""GPU parity at the full sizes the benchmark times, on sampled pixels the oracle fits one
+by one: the 64-frame batched mix (512x424, 640x480 and 1280x720 u16 with r in {3, 5, 7, 11}),
+frames through the serving loop, a 1280x720 frame at the largest window (37x37 dense), and
+a batch of the largest size (256 frames)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1707_00385_amd import scenes
+from tests.helpers import compare, log, oracle_pair
+
+pytestmark = pytest.mark.gpu
+
+K_ROBUST = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1707_00385_amd.api import Context
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _sample(depth, n, seed):
+    """n random pixels with depth (linear indices), seeded."""
+    idx = np.flatnonzero(depth.reshape(-1) > 0)
+    rng = np.random.default_rng([1707_00385, 40, seed])
+    return np.sort(rng.choice(idx, size=min(n, idx.size), replace=False))
+
+
+def _check_sampled(g, depth, cam, radius, iterations, name, n=800, seed=0, tol=1e-3):
+    px = _sample(depth, n, seed)
+    gs = {k: (v.reshape(-1, 3)[px] if k == "normal" else v.reshape(-1)[px])
+          for k, v in g.items() if isinstance(v, np.ndarray)}
+    o, oa = oracle_pair(depth, "u16", cam, radius, iterations, K_ROBUST, pixels=px)
+    return compare(gs, o, tol, name, o_alt=oa)
+
+
+def _sensor_pool():
+    pool = {}
+    for kind in ("tof", "vga", "hd"):
+        for j in range(3):
+            sc = scenes.sensor_frame(kind, seed_frame=j)
+            pool[(kind, j)] = (sc.depth_u16(), sc.camera)
+    return pool
+
+
+def test_batched_mix_at_full_size(ctx):
+    """The benchmark's 64-frame mix in one batch; every frame kind and radius sampled."""
+    import torch
+    from paper_1707_00385_amd.api import make_outputs, make_params, upload_depth
+    mix = scenes.batch_mix(64, seed=0)
+    pool = _sensor_pool()
+    dev = {k: upload_depth(d, "u16") for k, (d, _) in pool.items()}
+    jobs = []
+    for i, m in enumerate(mix):
+        d, cam = pool[(m["kind"], i % 3)]
+        t = dev[(m["kind"], i % 3)]
+        p = make_params(radius=m["radius"], iterations=m["iterations"])
+        o = make_outputs(t.shape[0], t.shape[1], t.device, normal=True, flags=True)
+        jobs.append((t, (cam.fx, cam.fy, cam.cx, cam.cy), p, o))
+    log(f"[case] batched mix: {len(jobs)} frames")
+    outs = ctx.fit_batch(jobs)
+    torch.cuda.synchronize()
+    seen = set()
+    for i, m in enumerate(mix):
+        key = (m["kind"], m["radius"])
+        if key in seen:
+            continue
+        seen.add(key)
+        d, cam = pool[(m["kind"], i % 3)]
+        g = {k: v.cpu().numpy() for k, v in outs[i].items()}
+        log(f"[case] item {i}: {m['kind']} {cam.width}x{cam.height} r={m['radius']} T={m['iterations']}")
+        _check_sampled(g, d, cam, m["radius"], m["iterations"], f"batch item {i}", seed=i)
+    assert len(seen) >= 9
+
+
+def test_served_sensor_frames_against_oracle(ctx):
+    """Frames of all three sensor kinds through the serving loop, sampled against the
+    oracle."""
+    from paper_1707_00385_amd import _lib
+    from paper_1707_00385_amd.api import Context, Server, device_view, make_params
+    import torch
+    pool = _sensor_pool()
+    reqs = [(("hd", 0), 11), (("vga", 1), 7), (("tof", 2), 5), (("hd", 1), 3), (("vga", 0), 9)]
+    sctx = Context(0)
+    srv = Server(sctx, memory_budget=256 << 20, max_batch=4, max_in_flight=2,
+                 outputs=_lib.QC_OUT_NORMAL | _lib.QC_OUT_FLAGS)
+    try:
+        tickets = {}
+        for j, (key, r) in enumerate(reqs):
+            d, cam = pool[key]
+            t = srv.submit(d, "u16", (cam.fx, cam.fy, cam.cx, cam.cy), make_params(radius=r, iterations=5), tag=j)
+            tickets[t] = j
+        done, t0 = [], time.time()
+        while len(done) < len(reqs):
+            done += srv.poll(16, wait_us=20000)
+            assert time.time() - t0 < 60
+        for c in done:
+            assert c.status == 0
+            key, r = reqs[c.tag]
+            d, cam = pool[key]
+            h, w = c.height, c.width
+            g = {"k1": device_view(c.k1, (h, w), torch.float32).cpu().numpy(),
+                 "k2": device_view(c.k2, (h, w), torch.float32).cpu().numpy(),
+                 "normal": device_view(c.normal, (h, w, 3), torch.float32).cpu().numpy(),
+                 "flags": device_view(c.flags, (h, w), torch.uint8).cpu().numpy()}
+            log(f"[case] served {key} {w}x{h} r={r}")
+            _check_sampled(g, d, cam, r, 5, f"served {key} r={r}", n=600, seed=100 + c.tag)
+            srv.release(c.ticket)
+    finally:
+        srv.close()
+        sctx.close()
+
+
+def test_hd_frame_at_the_largest_window(ctx):
+    """1280x720 u16 with the largest window, 37x37 dense (r = 18)."""
+    from tests.helpers import gpu_fit
+    sc = scenes.sensor_frame("hd", seed_frame=5)
+    d = sc.depth_u16()
+    log("[case] 1280x720 r=18")
+    g = gpu_fit(ctx, d, "u16", sc.camera, radius=18, iterations=5)
+    _check_sampled(g, d, sc.camera, 18, 5, "hd r=18", n=1000, seed=7)
+
+
+def test_largest_batch(ctx):
+    """QC_MAX_BATCH frames in one batch equal the per-frame calls; one more is refused."""
+    import torch
+    from paper_1707_00385_amd import _lib
+    from paper_1707_00385_amd.api import make_outputs, make_params, upload_depth
+    n = _lib.QC_MAX_BATCH
+    rng = np.random.default_rng([1707_00385, 41, 0])
+    jobs = []
+    for i in range(n + 1):
+        w, h = int(rng.integers(8, 40)), int(rng.integers(6, 30))
+        cam = scenes.Camera(w, h, 30.0, 30.0, (w - 1) / 2, (h - 1) / 2)
+        sc = scenes.cluttered_scene(cam, seed_frame=i, config_index=12, n_objects=2)
+        t = upload_depth(sc.depth_u16(), "u16")
+        p = make_params(radius=int(rng.integers(1, 5)), iterations=int(rng.integers(1, 4)))
+        o = make_outputs(h, w, t.device, normal=True, residual=True)
+        jobs.append((t, (cam.fx, cam.fy, cam.cx, cam.cy), p, o))
+    with pytest.raises(ValueError):
+        ctx.fit_batch(jobs)
+    log(f"[case] batch of {n} frames")
+    outs = ctx.fit_batch(jobs[:n])
+    torch.cuda.synchronize()
+    got = [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
+    for i, (t, K, p, _) in enumerate(jobs[:n]):
+        o = make_outputs(t.shape[0], t.shape[1], t.device, normal=True, residual=True)
+        ctx.fit(t, K, params=p, out=o)
+        torch.cuda.synchronize()
+        for k, v in o.items():
+            assert np.array_equal(got[i][k], v.cpu().numpy(), equal_nan=True), (i, k)
