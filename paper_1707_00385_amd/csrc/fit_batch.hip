@@ -40,12 +40,12 @@ void fit_batch_f32(const FitDesc* frames, const uint32_t* first_tile, const uint
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
 void refit_batch_f64(const FitDesc* frames, RefitList list) {
-    const uint32_t ranks = list.counts[0], entries = list.counts[1];
+    const uint32_t ranks = list.counts[0];
     const LaneGroup<kRefitLanes> grp{static_cast<int>(threadIdx.x % kRefitLanes)};
     for (;;) {
         const uint32_t base = next_ranks(&list.counts[3]);
         if (base >= ranks) break;
-        const uint32_t slot = __builtin_amdgcn_readfirstlane(entry_of(list, entries, base));
+        const uint32_t slot = entry_of(list, base);
         const uint32_t entry = __builtin_amdgcn_readfirstlane(list.entries[slot]);
         const int t = listed_thread(list.masks + 4 * static_cast<size_t>(slot),
                                     static_cast<int>(base - list.ranks[slot] + (threadIdx.x % 64) / kRefitLanes));

@@ -44,7 +44,7 @@ constexpr float kRejectMargin = 2e-5f;
 #define QC_F32_WAVES_PER_EU 3
 #endif
 #ifndef QC_F64_WAVES_PER_EU
-#define QC_F64_WAVES_PER_EU 3
+#define QC_F64_WAVES_PER_EU 2
 #endif
 #ifndef QC_F64_UNROLL
 #define QC_F64_UNROLL 3
@@ -670,7 +670,10 @@ __global__ void zero_counts(uint32_t* counts) {
 
 // FP64 pass: each listed pixel is fitted by a group of kRefitLanes lanes that split its
 // window rows, so a wave takes kChunk listed pixels at a time.
-constexpr int kRefitLanes = 4;
+#ifndef QC_REFIT_LANES
+#define QC_REFIT_LANES 4
+#endif
+constexpr int kRefitLanes = QC_REFIT_LANES;
 constexpr uint32_t kChunk = 64 / kRefitLanes;
 
 // Stages the depth samples of a (w + 2 halo) x (h + 2 halo) region whose top-left pixel
@@ -753,6 +756,8 @@ __device__ __forceinline__ void fit_tile_body(const FitDesc& d, int tx, int ty, 
                     const uint32_t slot = static_cast<uint32_t>(old >> 32);
                     list.entries[slot] = (frame << 24) | static_cast<uint32_t>(ty * tiles_across(d) + tx);
                     list.ranks[slot] = static_cast<uint32_t>(old);
+                    for (uint32_t c = 0; c < padded / kChunk; ++c)
+                        list.chunks[static_cast<uint32_t>(old) / kChunk + c] = slot;
 #pragma unroll
                     for (int w = 0; w < 4; ++w) list.masks[4 * slot + w] = m[w];
                 }
@@ -795,14 +800,10 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
     return pos;
 }
 
-// The entry holding rank q (q below counts[0]): the last entry whose first rank is <= q.
-__device__ __forceinline__ uint32_t entry_of(const RefitList& list, uint32_t entries, uint32_t q) {
-    uint32_t lo = 0, hi = entries - 1;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) / 2;
-        if (list.ranks[mid] <= q) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+// The entry holding the chunk of ranks that starts at `base` (a multiple of kChunk below
+// counts[0]), the same in every lane.
+__device__ __forceinline__ uint32_t entry_of(const RefitList& list, uint32_t base) {
+    return __builtin_amdgcn_readfirstlane(list.chunks[base / kChunk]);
 }
 
 // Thread (pixel of the tile) of the n-th listed pixel of an entry's 256-bit mask m, or -1

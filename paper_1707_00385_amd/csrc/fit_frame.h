@@ -46,7 +46,7 @@ template <int R, bool REJ, bool STR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
 void refit_f64(FitDesc d, RefitList list) {
     extern __shared__ float2 region[];
-    const uint32_t ranks = list.counts[0], entries = list.counts[1];
+    const uint32_t ranks = list.counts[0];
     const int tw = d.tile_w, th = 256 / tw;
     const int halo = max(R * (STR ? d.stride : 1), d.normal_radius);
     const int pitch = tw + 2 * halo;
@@ -55,7 +55,7 @@ void refit_f64(FitDesc d, RefitList list) {
     for (;;) {
         const uint32_t base = next_ranks(&list.counts[3]);
         if (base >= ranks) break;
-        const uint32_t slot = __builtin_amdgcn_readfirstlane(entry_of(list, entries, base));
+        const uint32_t slot = entry_of(list, base);
         const uint32_t tile = list.entries[slot] & 0xffffffu;
         const int bx = static_cast<int>(tile % across) * tw, by = static_cast<int>(tile / across) * th;
         stage_region(d, region, bx - halo, by - halo, pitch, th + 2 * halo);

@@ -35,6 +35,7 @@ struct RefitList {
     uint32_t* entries;   // per entry: (frame << 24) | tile index within the frame
     uint32_t* ranks;     // per entry: number of pixels listed in the entries before it
     uint64_t* masks;     // 4 words per entry: the listed pixels (bit t = thread t of the tile)
+    uint32_t* chunks;    // per 16 ranks (16 per entry at most): the entry holding them
     uint32_t* counts;    // kCountWords words, 8-byte aligned, zeroed by every launch:
                          // [0] ranks handed out (each entry's pixel count rounded up to a
                          // multiple of 16, so that 16 consecutive ranks never span two
@@ -44,7 +45,8 @@ struct RefitList {
 };
 constexpr int kCountWords = 8;
 
-// Bytes of entries + ranks + masks for `tiles` entries, and the list carved out of them.
+// Bytes of entries + ranks + masks + chunk table for `tiles` entries, and the list carved
+// out of them.
 size_t refit_list_bytes(int64_t tiles);
 RefitList refit_list(void* storage, int64_t tiles, uint32_t* counts);
 
