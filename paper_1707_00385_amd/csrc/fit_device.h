@@ -1,10 +1,11 @@
-// fit_device.h -- device code shared by the gfx950 kernels for per-pixel robust quadric-patch curvature fitting
-// (Spek, Li, Drummond, "A Fast Method For Computing Principal Curvatures From Range
-// Images", Section 3).
+// fit_device.h -- device code shared by the gfx950 kernels for per-pixel robust
+// quadric-patch curvature fitting (Spek, Li, Drummond, "A Fast Method For Computing
+// Principal Curvatures From Range Images", Section 3).
 //
-// One lane fits one pixel.  The fast pass stages a depth tile plus its halo in LDS and
-// runs the whole fit in FP32; the FP64 pass re-runs the identical sequence of steps in
-// double precision for a compacted list of pixels (or for every pixel).
+// The FP32 pass stages a depth tile plus its halo in LDS and one lane runs a pixel's
+// whole fit; pixels whose FP32 fit is judged unreliable are listed, and the FP64 pass
+// re-runs the identical sequence of steps in double precision for them, four lanes per
+// pixel (FP64 mode: one lane per pixel, every pixel).
 //
 // Arithmetic layout (exact in real arithmetic to the method's steps; chosen for FP32):
 //  * Centring (Eq. (5)) is done on the integer/native depth samples: with D the depth in
@@ -40,6 +41,8 @@ constexpr int kTileW = 16;
 // not trusted (about 10x the FP32 error of e^2 for residuals at the noise level).
 constexpr float kRejectMargin = 2e-5f;
 
+// Compile-time tuning (measured defaults): waves per SIMD of the FP32 pass and of the
+// FP64 recomputation, neighbours per unrolled step of the FP64 window loops.
 #ifndef QC_F32_WAVES_PER_EU
 #define QC_F32_WAVES_PER_EU 3
 #endif
@@ -49,7 +52,6 @@ constexpr float kRejectMargin = 2e-5f;
 #ifndef QC_F64_UNROLL
 #define QC_F64_UNROLL 3
 #endif
-
 
 // ---------------------------------------------------------------------------- scalars
 template <typename T> __device__ __forceinline__ T fmaT(T a, T b, T c);
