@@ -166,25 +166,31 @@ struct Geometry {
 };
 
 // A pixel's fit may be shared by NP consecutive lanes: lane `part` takes the window rows
-// dv = -r + part, -r + part + NP, ..., and sum() adds a value over the group by an xor
+// dv = -r + part, -r + part + NP, ..., and sum() adds a value over the group by a
 // butterfly, which leaves every lane of the group with the same bits (the additions are
 // the same pairs in the same order up to commutation).  NP = 1 is one lane per pixel.
-// Value of lane (this lane xor M) within its quad of four lanes (DPP quad permutation).
+//
+// Step M of the butterfly adds the value of a partner lane in the other half of the
+// aligned group of 2M lanes.  Every lane of an M-lane half already holds that half's sum,
+// so any partner there will do: the xor partner within a quad for M = 1, 2 (DPP quad
+// permutations), the mirror image within 8 or 16 lanes for M = 4, 8 (DPP row_half_mirror,
+// row_mirror), a cross-row shuffle beyond.  Each source lane lies in the same row of 16,
+// so every lane is written and the old value of the destination is never used.
 template <int M>
-__device__ __forceinline__ int quad_xor(int v) {
-    constexpr int ctrl = M == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] / [2,3,0,1]
-    return __builtin_amdgcn_update_dpp(0, v, ctrl, 0xF, 0xF, false);
+__device__ __forceinline__ int dpp_partner(int v) {
+    constexpr int ctrl = M == 1 ? 0xB1 : M == 2 ? 0x4E : M == 4 ? 0x141 : 0x140;
+    return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, false);
 }
 template <int M, typename T>
-__device__ __forceinline__ T lane_xor(T x) {
-    if constexpr (M < 4) {
+__device__ __forceinline__ T partner(T x) {
+    if constexpr (M <= 8) {
         if constexpr (sizeof(T) == 8) {
             const uint64_t b = __builtin_bit_cast(uint64_t, x);
-            const uint32_t lo = static_cast<uint32_t>(quad_xor<M>(static_cast<int>(b)));
-            const uint32_t hi = static_cast<uint32_t>(quad_xor<M>(static_cast<int>(b >> 32)));
+            const uint32_t lo = static_cast<uint32_t>(dpp_partner<M>(static_cast<int>(b)));
+            const uint32_t hi = static_cast<uint32_t>(dpp_partner<M>(static_cast<int>(b >> 32)));
             return __builtin_bit_cast(T, (static_cast<uint64_t>(hi) << 32) | lo);
         } else {
-            return __builtin_bit_cast(T, quad_xor<M>(__builtin_bit_cast(int, x)));
+            return __builtin_bit_cast(T, dpp_partner<M>(__builtin_bit_cast(int, x)));
         }
     } else {
         return __shfl_xor(x, M);
@@ -196,12 +202,12 @@ struct LaneGroup {
     int part;
     template <typename T>
     __device__ __forceinline__ T sum(T x) const {
-        if constexpr (NP > 1) x += lane_xor<1>(x);
-        if constexpr (NP > 2) x += lane_xor<2>(x);
-        if constexpr (NP > 4) x += lane_xor<4>(x);
-        if constexpr (NP > 8) x += lane_xor<8>(x);
-        if constexpr (NP > 16) x += lane_xor<16>(x);
-        if constexpr (NP > 32) x += lane_xor<32>(x);
+        if constexpr (NP > 1) x += partner<1>(x);
+        if constexpr (NP > 2) x += partner<2>(x);
+        if constexpr (NP > 4) x += partner<4>(x);
+        if constexpr (NP > 8) x += partner<8>(x);
+        if constexpr (NP > 16) x += partner<16>(x);
+        if constexpr (NP > 32) x += partner<32>(x);
         return x;
     }
 };
@@ -230,11 +236,29 @@ __device__ __forceinline__ void for_window(const Src& src, int radius, const Lan
             row_end();
         }
     } else if constexpr (U >= 2) {
+        // U neighbours at a time; the samples of the next U are read before this group is
+        // processed, so their latency overlaps its arithmetic (reads past the row's end
+        // are clamped to its last sample and not used)
+        const int n = 2 * r + 1, nfull = n / U * U;
 #pragma unroll 1
         for (int dv = first; dv <= r; dv += NP) {
             auto row = src.row(dv);
-#pragma unroll U
-            for (int du = -r; du <= r; ++du) f(row[du], du, dv);
+            float2 cur[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) cur[k] = row[min(k, n - 1) - r];
+#pragma unroll 1
+            for (int i0 = 0; i0 < nfull; i0 += U) {
+                float2 nxt[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) nxt[k] = row[min(i0 + U + k, n - 1) - r];
+#pragma unroll
+                for (int k = 0; k < U; ++k) f(cur[k], i0 + k - r, dv);
+#pragma unroll
+                for (int k = 0; k < U; ++k) cur[k] = nxt[k];
+            }
+#pragma unroll
+            for (int k = 0; k < U - 1; ++k)
+                if (nfull + k < n) f(cur[k], nfull + k - r, dv);
             row_end();
         }
     } else {
@@ -689,6 +713,53 @@ __device__ __forceinline__ void stage_region(const FitDesc& d, float2* lds, int 
     __syncthreads();
 }
 
+// The same for the FP64 kernels, whose workgroups are one wave: each lane reads B samples
+// before it writes any, so that their loads are in flight together (one short loop per
+// tile instead of one memory round trip per sample).  Coordinates outside the image are
+// clamped for the read and marked missing.
+template <typename T>
+__device__ __forceinline__ float sample_value(T x) { return static_cast<float>(x); }
+template <>
+__device__ __forceinline__ float sample_value(__half x) { return __half2float(x); }
+
+template <typename T, int B>
+__device__ __forceinline__ void stage_batched(const FitDesc& d, float2* lds, int x0, int y0,
+                                              int pitch, int total) {
+    const float inv_pitch = 1.f / static_cast<float>(pitch);
+    const int step = static_cast<int>(blockDim.x);
+    for (int i0 = threadIdx.x; i0 < total; i0 += B * step) {
+        float z[B];
+        bool in[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int i = min(i0 + k * step, total - 1);
+            // i / pitch for i < 2^16: (i + 1/2) / pitch lies at least 1/(2 pitch) away
+            // from an integer, far more than the rounding of the float product
+            const int ly = static_cast<int>((static_cast<float>(i) + 0.5f) * inv_pitch);
+            const int x = x0 + i - ly * pitch, y = y0 + ly;
+            in[k] = x >= 0 && y >= 0 && x < d.width && y < d.height;
+            const int xc = min(max(x, 0), d.width - 1), yc = min(max(y, 0), d.height - 1);
+            const T* row = reinterpret_cast<const T*>(static_cast<const char*>(d.depth) +
+                                                      static_cast<int64_t>(yc) * d.pitch);
+            z[k] = sample_value(row[xc]);
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int i = i0 + k * step;
+            const bool ok = in[k] && z[k] > 0.f && z[k] <= 3.0e38f;
+            if (i < total) lds[i] = make_float2(ok ? z[k] : 0.f, ok ? 1.f : INFINITY);
+        }
+    }
+}
+__device__ __forceinline__ void stage_region_wave(const FitDesc& d, float2* lds, int x0, int y0,
+                                                  int pitch, int rows) {
+    constexpr int B = 8;
+    if (d.format == 0) stage_batched<uint16_t, B>(d, lds, x0, y0, pitch, pitch * rows);
+    else if (d.format == 1) stage_batched<__half, B>(d, lds, x0, y0, pitch, pitch * rows);
+    else stage_batched<float, B>(d, lds, x0, y0, pitch, pitch * rows);
+    __syncthreads();
+}
+
 template <typename Real>
 __device__ __forceinline__ PixelFit<Real> missing_pixel() {
     PixelFit<Real> r;
@@ -714,7 +785,10 @@ __device__ __forceinline__ void fit_tile_body(const FitDesc& d, int tx, int ty, 
     const int tw = d.tile_w, th = blockDim.x / tw;
     const int halo = max(R * (STR ? d.stride : 1), d.normal_radius);
     const int pitch = tw + 2 * halo;
-    stage_region(d, tile, tx * tw - halo, ty * th - halo, pitch, th + 2 * halo);
+    if constexpr (sizeof(Real) == 8)
+        stage_region_wave(d, tile, tx * tw - halo, ty * th - halo, pitch, th + 2 * halo);
+    else
+        stage_region(d, tile, tx * tw - halo, ty * th - halo, pitch, th + 2 * halo);
     const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
     const int u = tx * tw + lx, v = ty * th + ly;
     const bool mixed = sizeof(Real) == 4 && d.precision == 0;
@@ -811,13 +885,15 @@ __device__ __forceinline__ uint32_t entry_of(const RefitList& list, uint32_t bas
 // Thread (pixel of the tile) of the n-th listed pixel of an entry's 256-bit mask m, or -1
 // when the entry lists no more than n pixels.
 __device__ __forceinline__ int listed_thread(const uint64_t* m, int n) {
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const int c = __popcll(m[w]);
-        if (n < c) return w * 64 + nth_set_bit(m[w], n);
-        n -= c;
-    }
-    return -1;
+    // all four words are read up front (one memory round trip)
+    const uint64_t w0 = m[0], w1 = m[1], w2 = m[2], w3 = m[3];
+    const int c0 = __popcll(w0), c1 = c0 + __popcll(w1), c2 = c1 + __popcll(w2);
+    const int c3 = c2 + __popcll(w3);
+    if (n >= c3) return -1;
+    if (n < c0) return nth_set_bit(w0, n);
+    if (n < c1) return 64 + nth_set_bit(w1, n - c0);
+    if (n < c2) return 128 + nth_set_bit(w2, n - c1);
+    return 192 + nth_set_bit(w3, n - c2);
 }
 
 // The next kChunk ranks for this wave (the same value in every lane).

@@ -58,7 +58,7 @@ void refit_f64(FitDesc d, RefitList list) {
         const uint32_t slot = entry_of(list, base);
         const uint32_t tile = list.entries[slot] & 0xffffffu;
         const int bx = static_cast<int>(tile % across) * tw, by = static_cast<int>(tile / across) * th;
-        stage_region(d, region, bx - halo, by - halo, pitch, th + 2 * halo);
+        stage_region_wave(d, region, bx - halo, by - halo, pitch, th + 2 * halo);
         const int t = listed_thread(list.masks + 4 * static_cast<size_t>(slot),
                                     static_cast<int>(base - list.ranks[slot] + threadIdx.x / kRefitLanes));
         if (t >= 0) {
