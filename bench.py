@@ -513,7 +513,7 @@ def main() -> int:
             traffic = prof.get("hbm_bytes_per_launch")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": traffic, "kernel": "fit_tile<float,7,16>",
+                "traffic": traffic, "kernel": "fit_tile_f32<7, false, false>",
                 "kernel_ms": round(fit_ms, 4), "algorithmic_gflop_per_launch": round(flops_per_launch / 1e9, 3)}
 
     result = {

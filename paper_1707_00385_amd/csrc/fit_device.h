@@ -388,10 +388,12 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         R[2][0] = -wy;                    R[2][1] = wx;                     R[2][2] = n0z;
     }
     Real tz = 0, A = 0, B = 0, C = 0;     // patch coefficients in units of h
-    Acc kappa_max = 0, last_step = 0;
+    Acc last_step = 0;
+    bool cond_ok = true;                  // pivot ratio within cond_max at every iteration
     bool near = false;                    // an FP32 rejection decision was too close to call
     // window half-extent r Z_c / fx in units of h
     const Acc hwin = Acc(radius * step) * Acc(g.Dc) * Acc(s) / Acc(fx) * Acc(g.ih);
+    const Acc ihwin = Acc(1) / hwin;
 
     for (int it = 0; it < d.iterations; ++it) {
         // R' = R G: maps m straight to the rotated, scaled, centred point s = R p'/h.
@@ -520,7 +522,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
             singular |= !(Hm[i][i] > Acc(0));
             dsc[i] = Hm[i][i] > Acc(0) ? rsqrtT(Hm[i][i]) : Acc(0);
         }
-        Acc L[6][6], dp[6];
+        Acc L[6][6], dp[6], idp[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
             Acc dj = Acc(1);   // equilibrated diagonal
@@ -528,6 +530,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
             for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k] * dp[k];
             dp[j] = dj;
             const Acc idj = dj > Acc(0) ? Acc(1) / dj : Acc(0);
+            idp[j] = idj;
 #pragma unroll
             for (int i = j + 1; i < 6; ++i) {
                 Acc sij = dsc[i] * dsc[j] * Hm[j][i];
@@ -545,7 +548,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
             if (fp32) out.flags = kFlagIll;
             return out;
         }
-        kappa_max = fmax(kappa_max, pmax / pmin);
+        cond_ok = cond_ok && pmax <= Acc(d.cond_max) * pmin;
         Acc y[6], b[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
@@ -556,7 +559,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         }
 #pragma unroll
         for (int i = 5; i >= 0; --i) {
-            Acc sb = y[i] / dp[i];
+            Acc sb = y[i] * idp[i];
 #pragma unroll
             for (int k = i + 1; k < 6; ++k) sb -= L[k][i] * b[k];
             b[i] = sb;
@@ -566,7 +569,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         // Size of the update in window units (angles in radians, t_z in window
         // half-extents, curvatures times the half-extent): how far from converged.
         last_step = fmax(fmax(fabs(b[0]), fabs(b[1])),
-                         fmax(fabs(b[2]) / hwin, hwin * fmax(fmax(fabs(b[3]), fabs(b[4])), fabs(b[5]))));
+                         fmax(fabs(b[2]) * ihwin, hwin * fmax(fmax(fabs(b[3]), fabs(b[4])), fabs(b[5]))));
 
         // Update (Section 3.2.3): R <- Exp([(-b0, -b1, 0)]x) R (exact Rodrigues),
         // t_z -= b2, A -= b3, B -= b4, C -= b5.
@@ -576,8 +579,9 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
             Real st = Real(1), c1 = Real(0.5);
             if (th2 > Real(0)) {
                 const Real th = sqrtT(th2);
-                st = sinT(th) / th;                         // sin(th)/th
-                const Real sh = sinT(Real(0.5) * th) / th;  // sin(th/2)/th
+                const Real ith = Real(1) / th;
+                st = sinT(th) * ith;                        // sin(th)/th
+                const Real sh = sinT(Real(0.5) * th) * ith; // sin(th/2)/th
                 c1 = Real(2) * sh * sh;                     // (1-cos th)/th^2
             }
             const Real E00 = Real(1) - c1 * w1 * w1, E01 = c1 * w0 * w1, E02 = st * w1;
@@ -671,7 +675,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
     out.n[1] = R[2][1];
     out.n[2] = R[2][2];
     out.flags = kFlagValid | (fp32 ? 0 : kFlagFp64);
-    if (fp32 && (ill || near || !(kappa_max <= Acc(d.cond_max)) || !(last_step <= Acc(d.step_max))))
+    if (fp32 && (ill || near || !cond_ok || !(last_step <= Acc(d.step_max))))
         out.flags |= kFlagIll;
     return out;
 }
