@@ -109,7 +109,8 @@ def sensor_pool(per_kind: int = 3) -> dict:
     return _POOL
 
 
-def measure_served(ctx, duration_s: float = 4.0, fps: float = 240.0, sensors: int = 6) -> dict:
+def measure_served(ctx, duration_s: float = 4.0, fps: float = 240.0, sensors: int = 6,
+                   saturated: bool = True, warm_up: bool = True) -> dict:
     """The serving form on a seeded Poisson trace (sensors with fixed resolutions, per-frame
     window radius 3..11, T = 5) and in a saturating run (the whole trace queued at once),
     against the plain path (one qc_fit per frame in arrival order, one frame in flight).
@@ -188,12 +189,15 @@ def measure_served(ctx, duration_s: float = 4.0, fps: float = 240.0, sensors: in
                 "p50_ms": round(float(np.percentile(lat, 50)), 3),
                 "p99_ms": round(float(np.percentile(lat, 99)), 3), "wall_s": round(span, 3)}
 
-    plain(False)   # warm-up of every radius variant
+    if warm_up:
+        plain(False)   # warm-up of every radius variant
     res = {"trace": f"{sensors} sensors, Poisson arrivals {fps:.0f} frames/s aggregate over "
                     f"{duration_s:.0f} s (seeded), 512x424 ToF / 640x480 / 1280x720 u16, "
                     f"r in 3..11, T=5, {len(trace)} frames",
-           "served_realtime": served(True), "plain_realtime": plain(True),
-           "served_saturated": served(False), "plain_saturated": plain(False)}
+           "served_realtime": served(True), "plain_realtime": plain(True)}
+    if saturated:
+        res["served_saturated"] = served(False)
+        res["plain_saturated"] = plain(False)
     return res
 
 
@@ -557,6 +561,21 @@ def main() -> int:
                                                 sv["plain_saturated"]["pixels_per_s"], 3),
             "realtime_p99_ms": {"served": sv["served_realtime"]["p99_ms"],
                                 "plain": sv["plain_realtime"]["p99_ms"]}}
+        # latency against load: the same sensors at lower aggregate rates
+        sweep = []
+        for fps in (30.0, 60.0, 120.0):
+            lv = measure_served(ctx, duration_s=3.0, fps=fps, saturated=False, warm_up=False)
+            sweep.append({"fps": fps, "frames": lv["served_realtime"]["frames"],
+                          "served_p50_ms": lv["served_realtime"]["p50_ms"],
+                          "served_p99_ms": lv["served_realtime"]["p99_ms"],
+                          "plain_p50_ms": lv["plain_realtime"]["p50_ms"],
+                          "plain_p99_ms": lv["plain_realtime"]["p99_ms"]})
+        sweep.append({"fps": 240.0, "frames": sv["served_realtime"]["frames"],
+                      "served_p50_ms": sv["served_realtime"]["p50_ms"],
+                      "served_p99_ms": sv["served_realtime"]["p99_ms"],
+                      "plain_p50_ms": sv["plain_realtime"]["p50_ms"],
+                      "plain_p99_ms": sv["plain_realtime"]["p99_ms"]})
+        result["served_load_sweep"] = sweep
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(frames[0], cam)
     print(json.dumps(result), flush=True)
