@@ -38,8 +38,11 @@ void fit_batch_f32(const FitDesc* frames, const uint32_t* first_tile, const uint
     }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
+// Persistent FP64 pass over the listed pixels of all frames of a batch, one wave per
+// workgroup, as the per-frame recomputation: each chunk's tile is staged in LDS.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(QC_F64_WAVES_PER_EU)))
 void refit_batch_f64(const FitDesc* frames, RefitList list) {
+    extern __shared__ float2 region[];
     const uint32_t ranks = list.counts[0];
     const LaneGroup<kRefitLanes> grp{static_cast<int>(threadIdx.x % kRefitLanes)};
     for (;;) {
@@ -48,13 +51,11 @@ void refit_batch_f64(const FitDesc* frames, RefitList list) {
         const uint32_t slot = entry_of(list, base);
         const uint32_t entry = __builtin_amdgcn_readfirstlane(list.entries[slot]);
         const int t = listed_thread(list.masks + 4 * static_cast<size_t>(slot),
-                                    static_cast<int>(base - list.ranks[slot] + (threadIdx.x % 64) / kRefitLanes));
+                                    static_cast<int>(base - list.ranks[slot] + threadIdx.x / kRefitLanes));
         const FitDesc d = frames[entry >> 24];
-        if (t >= 0) {
-            with_radius(d.radius, [&](auto rc) {
-                refit_pixel_global<decltype(rc)::value>(d, entry & 0xffffffu, t, grp);
-            });
-        }
+        with_radius(d.radius, [&](auto rc) {
+            refit_chunk<decltype(rc)::value>(d, entry & 0xffffffu, t, grp, region);
+        });
     }
 }
 
@@ -70,9 +71,14 @@ size_t batch_lds_bytes() {
     return m;
 }
 
+size_t batch_refit_lds_bytes(const FitDesc& d) {
+    const int halo = d.radius > d.normal_radius ? d.radius : d.normal_radius;
+    return lds_bytes(d.tile_w, 256 / d.tile_w, halo);
+}
+
 hipError_t launch_fit_batch(const FitDesc* frames, const uint32_t* first_tile,
-                            const uint32_t* header, int workgroups, const RefitList& list,
-                            hipStream_t stream, hipEvent_t* events) {
+                            const uint32_t* header, int workgroups, size_t refit_lds,
+                            const RefitList& list, hipStream_t stream, hipEvent_t* events) {
     hipError_t e;
     hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, list.counts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -82,7 +88,7 @@ hipError_t launch_fit_batch(const FitDesc* frames, const uint32_t* first_tile,
                        header, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (events && (e = hipEventRecord(events[1], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(refit_batch_f64, dim3(workgroups), dim3(256), 0, stream, frames, list);
+    hipLaunchKernelGGL(refit_batch_f64, dim3(4 * workgroups), dim3(64), refit_lds, stream, frames, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (events && (e = hipEventRecord(events[2], stream)) != hipSuccess) return e;
     return hipSuccess;

@@ -117,41 +117,6 @@ struct LdsStridedSource {
         return LdsStridedRow{centre + j * step * pitch, step};
     }
 };
-// Neighbourhood read straight from the depth image (L2-resident), with the same (D, c)
-// pairs as the LDS copy.  The read is branch-free, so that the window loop stays straight-
-// line code whose loads can be issued ahead: coordinates are clamped into the image, a
-// sample is read as two 16-bit halves (the second one 2 bytes on for F32, the same half
-// otherwise) and decoded by the format, and outside samples are marked missing afterwards.
-struct GlobalRow {
-    const char* row;   // depth row clamped into the image
-    int x, wm1, shift, hi_off, format;
-    bool inside;       // the unclamped row lies in the image
-    __device__ __forceinline__ float2 operator[](int du) const {
-        const int xi = x + du;
-        const bool in = inside && static_cast<unsigned>(xi) <= static_cast<unsigned>(wm1);
-        const int xc = min(max(xi, 0), wm1);
-        const char* p = row + (static_cast<int64_t>(xc) << shift);
-        const uint32_t lo = *reinterpret_cast<const uint16_t*>(p);
-        const uint32_t hi = *reinterpret_cast<const uint16_t*>(p + hi_off);
-        const float zu = static_cast<float>(lo);
-        const float zh = __half2float(__ushort_as_half(static_cast<unsigned short>(lo)));
-        const float zf = __uint_as_float((hi << 16) | lo);
-        const float z = format == 0 ? zu : (format == 1 ? zh : zf);
-        const bool ok = in && z > 0.f && z <= 3.0e38f;   // excludes 0, negatives, inf and NaN
-        return make_float2(ok ? z : 0.f, ok ? 1.f : INFINITY);
-    }
-};
-struct GlobalSource {
-    const char* depth;
-    int64_t pitch;
-    int width, height, format, u, v;
-    __device__ __forceinline__ GlobalRow row(int dv) const {
-        const int y = v + dv;
-        const int yc = min(max(y, 0), height - 1);
-        return GlobalRow{depth + static_cast<int64_t>(yc) * pitch, u, width - 1, format == 2 ? 2 : 1,
-                         format == 2 ? 2 : 0, format, static_cast<unsigned>(y) < static_cast<unsigned>(height)};
-    }
-};
 // ---------------------------------------------------------------------------- one pixel
 template <typename Real>
 struct PixelFit {
@@ -907,21 +872,29 @@ __device__ __forceinline__ uint32_t next_ranks(uint32_t* counter) {
     return __builtin_amdgcn_readfirstlane(base);
 }
 
-// FP64 pass over the listed pixels of a batch, reading the windows from the depth images.
-// Every chunk lies in one entry, hence one frame, so the frame's descriptor and window
-// radius are uniform across the wave.
+// FP64 recomputation of one chunk of a batch: the chunk lies in one entry, hence in one
+// tile of one frame, so the frame's descriptor and window radius are uniform across the
+// wave.  The wave stages that tile plus halo in its LDS `region` (sized by the host for
+// the largest region of the batch) and fits its pixels from there, `thread` being the
+// listed pixel's thread in the tile (-1 for the lanes of a part-filled chunk).
 template <int R>
-__device__ __forceinline__ void refit_pixel_global(const FitDesc& d, uint32_t tile, int thread,
-                                                   const LaneGroup<kRefitLanes>& grp) {
+__device__ __forceinline__ void refit_chunk(const FitDesc& d, uint32_t tile, int thread,
+                                            const LaneGroup<kRefitLanes>& grp, float2* region) {
     const int tw = d.tile_w, th = 256 / tw;
     const int across = tiles_across(d);
-    const int u = static_cast<int>(tile % across) * tw + thread % tw;
-    const int v = static_cast<int>(tile / across) * th + thread / tw;
-    const float Dc = sample_or_missing(d, u, v).x;   // a listed pixel has its depth
-    const GlobalSource src{static_cast<const char*>(d.depth), d.pitch, d.width, d.height, d.format, u, v};
-    const PixelFit<double> r = fit_pixel<double, R, kRefitLanes>(d, src, src, u, v, Dc,
-                                                                 d.residual != nullptr, grp);
-    if (grp.part == 0) store_pixel(d, static_cast<int64_t>(v) * d.width + u, r);
+    const int bx = static_cast<int>(tile % across) * tw, by = static_cast<int>(tile / across) * th;
+    const int halo = max(R, d.normal_radius);
+    const int pitch = tw + 2 * halo;
+    stage_region_wave(d, region, bx - halo, by - halo, pitch, th + 2 * halo);
+    if (thread >= 0) {
+        const int lx = thread % tw, ly = thread / tw;
+        const float2* centre = region + (ly + halo) * pitch + (lx + halo);
+        const LdsSource src{centre, pitch};
+        const PixelFit<double> r = fit_pixel<double, R, kRefitLanes>(d, src, src, bx + lx, by + ly, centre->x,
+                                                                     d.residual != nullptr, grp);
+        if (grp.part == 0) store_pixel(d, static_cast<int64_t>(by + ly) * d.width + bx + lx, r);
+    }
+    __syncthreads();   // the next chunk re-stages the region
 }
 
 inline size_t lds_bytes(int tile_w, int tile_h, int halo) {

@@ -70,11 +70,15 @@ bool valid_tile_width(int tile_w);
 // persistent FP32 pass of `workgroups` workgroups over all tiles, then one persistent FP64
 // pass over the listed pixels of all frames.  List capacity: first_tile[n] entries; at
 // most 256 frames.
+// `refit_lds`: dynamic LDS of the FP64 pass's one-wave workgroups, at least the largest
+// batch_refit_lds_bytes() over the batch's frames.
 hipError_t launch_fit_batch(const FitDesc* frames, const uint32_t* first_tile,
-                            const uint32_t* header, int workgroups, const RefitList& list,
-                            hipStream_t stream, hipEvent_t* events = nullptr);
+                            const uint32_t* header, int workgroups, size_t refit_lds,
+                            const RefitList& list, hipStream_t stream, hipEvent_t* events = nullptr);
 
-// Dynamic LDS of the batched kernels (largest tile shape at the largest radius).
+// Dynamic LDS of the batched FP32 pass (largest tile shape at the largest radius), and
+// the region the FP64 pass stages for a tile of frame `d`.
 size_t batch_lds_bytes();
+size_t batch_refit_lds_bytes(const FitDesc& d);
 
 }  // namespace qc

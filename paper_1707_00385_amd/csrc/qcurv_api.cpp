@@ -34,6 +34,7 @@ struct BatchSlot {
     void* list = nullptr;           // refit list storage for `capacity` entries
     uint32_t* counts = nullptr;
     int64_t capacity = 0;           // refit list entries
+    size_t refit_lds = 0;           // LDS of the captured FP64 pass's workgroups
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;      // recorded after the slot's last use
@@ -181,12 +182,13 @@ void free_slot(BatchSlot& s) {
     s.graph = nullptr;
     s.list = nullptr;
     s.capacity = 0;
+    s.refit_lds = 0;
 }
 
-// Makes `s` hold scratch for `entries` tiles and a graph bound to it.  The graph is the
-// staging upload, a counter-reset kernel and the two persistent passes; it holds no
-// memset node.
-qc_status prepare_slot(qc_context* ctx, BatchSlot& s, int64_t entries) {
+// Makes `s` hold scratch for `entries` tiles and a graph bound to it whose FP64 pass has
+// at least `refit_lds` bytes of LDS per workgroup.  The graph is the staging upload, a
+// counter-reset kernel and the two persistent passes; it holds no memset node.
+qc_status prepare_slot(qc_context* ctx, BatchSlot& s, int64_t entries, size_t refit_lds) {
     hipError_t e;
     if (!s.host) {
         void* h = nullptr;
@@ -201,20 +203,24 @@ qc_status prepare_slot(qc_context* ctx, BatchSlot& s, int64_t entries) {
         s.counts = static_cast<uint32_t*>(c);
         if ((e = hipEventCreate(&s.done)) != hipSuccess) return hip_fail(ctx, e);
     }
-    if (s.capacity >= entries && s.exec) return QC_OK;
+    if (s.capacity >= entries && s.refit_lds >= refit_lds && s.exec) return QC_OK;
+    // keep the larger of the old and new needs, so that alternating batches do not
+    // capture again and again
+    const int64_t cap = std::max<int64_t>({entries, s.capacity, 1 << 16});
+    const size_t lds = std::max(refit_lds, s.refit_lds);
     free_slot(s);
-    const int64_t cap = std::max<int64_t>(entries, 1 << 16);
     void* p = nullptr;
     if ((e = hipMalloc(&p, qc::refit_list_bytes(cap))) != hipSuccess) return hip_fail(ctx, e);
     s.list = p;
     s.capacity = cap;
+    s.refit_lds = lds;
     hipStream_t cs = ctx->capture_stream;
     if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return hip_fail(ctx, e);
     hipError_t le = hipMemcpyAsync(s.dev, s.host, sizeof(BatchStaging), hipMemcpyHostToDevice, cs);
     if (le == hipSuccess)
         le = qc::launch_fit_batch(s.dev->frames, s.dev->first_tile, s.dev->header, 4 * ctx->cus,
-                                  qc::refit_list(s.list, s.capacity, s.counts), cs);
+                                  s.refit_lds, qc::refit_list(s.list, s.capacity, s.counts), cs);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
     if (le != hipSuccess) {
@@ -373,7 +379,9 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
         if ((e = hipEventSynchronize(s.done)) != hipSuccess) return hip_fail(ctx, e);
         s.in_flight = false;
     }
-    if ((st = prepare_slot(ctx, s, first[n])) != QC_OK) return st;
+    size_t refit_lds = 0;
+    for (int32_t j = 0; j < n; ++j) refit_lds = std::max(refit_lds, qc::batch_refit_lds_bytes(descs[j]));
+    if ((st = prepare_slot(ctx, s, first[n], refit_lds)) != QC_OK) return st;
     std::memcpy(s.host->frames, descs.data(), sizeof(qc::FitDesc) * n);
     std::memcpy(s.host->first_tile, first.data(), sizeof(uint32_t) * (n + 1));
     s.host->header[0] = static_cast<uint32_t>(n);
@@ -394,7 +402,8 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
         ctx->pending.insert(ctx->pending.end(), ev, ev + 3);
         if ((e = hipMemcpyAsync(s.dev, s.host, sizeof(BatchStaging), hipMemcpyHostToDevice, hs)) != hipSuccess ||
             (e = qc::launch_fit_batch(s.dev->frames, s.dev->first_tile, s.dev->header, 4 * ctx->cus,
-                                      qc::refit_list(s.list, s.capacity, s.counts), hs, ev)) != hipSuccess)
+                                      s.refit_lds, qc::refit_list(s.list, s.capacity, s.counts), hs,
+                                      ev)) != hipSuccess)
             return hip_fail(ctx, e);
     } else if ((e = hipGraphLaunch(s.exec, hs)) != hipSuccess) {
         return hip_fail(ctx, e);
