@@ -142,7 +142,9 @@ typedef struct {
 
 /* Fits up to QC_MAX_BATCH frames of any sizes, window radii and iteration counts with one
  * persistent FP32 launch over all their tiles and one persistent FP64 recomputation
- * launch (MIXED), replayed from a HIP graph the context captures once.  Each item's
+ * launch (MIXED), replayed from a HIP graph the context captures once per batch slot (and
+ * again, in the call, when a batch needs a larger list or a larger LDS staging region than
+ * any before it; that call may wait for work in flight on the device).  Each item's
  * outputs equal, bit for bit, those of qc_fit on the same item.  All items must use the
  * same precision, MIXED or FP32 (FP64 frames go through qc_fit).  A batch holding an item
  * with reject = 1 or stride > 1 runs as per-frame launches in item order instead.  At most two batches

@@ -187,3 +187,33 @@ def test_tune_records_and_round_trips(ctx):
         line = open(path).read().split()
         assert line == ["128", "96", "3", "3", str(tw)]
         ctx.tune_load(path)
+
+
+def test_batches_needing_more_lds_recapture():
+    """The batched FP64 pass stages each chunk's tile in LDS sized for the batch's largest
+    region, fixed when the slot's graph is captured: a later batch with a larger region
+    (r = 18, 64-wide tiles: 100 x 40 samples) must be captured again, and batches with
+    small regions after it must still be right.  Every item equals its per-frame call."""
+    import torch
+    from paper_1707_00385_amd.api import Context, make_outputs, make_params, upload_depth
+    c = Context(0)
+    try:
+        cams = [scenes.Camera(90, 70, 80.0, 80.0, 44.5, 34.5), scenes.Camera(130, 50, 90.0, 90.0, 64.5, 24.5)]
+        frames = []
+        for i, cam in enumerate(cams):
+            sc = scenes.cluttered_scene(cam, seed_frame=60 + i, config_index=3)
+            frames.append((cam, upload_depth(sc.depth_u16(), "u16")))
+        for step, (r, tw) in enumerate(((2, 16), (18, 64), (3, 8), (18, 64), (1, 32))):
+            bj = []
+            for cam, t in frames:
+                p = make_params(radius=r, iterations=3, tile_width=tw)
+                bj.append((t, (cam.fx, cam.fy, cam.cx, cam.cy), p,
+                           make_outputs(cam.height, cam.width, t.device, normal=True, residual=True)))
+            log(f"[case] batch {step}: r={r} tile width {tw}")
+            outs = c.fit_batch(bj)
+            torch.cuda.synchronize()
+            for i, ((t, K, p, _), o) in enumerate(zip(bj, outs)):
+                single = _run_single(c, t, frames[i][0], p)
+                _equal({k: v.cpu().numpy() for k, v in o.items()}, single, f"batch {step} frame {i}")
+    finally:
+        c.close()
