@@ -32,11 +32,11 @@ def _sample(depth, n, seed):
     return np.sort(rng.choice(idx, size=min(n, idx.size), replace=False))
 
 
-def _check_sampled(g, depth, cam, radius, iterations, name, n=800, seed=0, tol=1e-3):
+def _check_sampled(g, depth, cam, radius, iterations, name, n=800, seed=0, tol=1e-3, fmt="u16"):
     px = _sample(depth, n, seed)
     gs = {k: (v.reshape(-1, 3)[px] if k == "normal" else v.reshape(-1)[px])
           for k, v in g.items() if isinstance(v, np.ndarray)}
-    o, oa = oracle_pair(depth, "u16", cam, radius, iterations, K_ROBUST, pixels=px)
+    o, oa = oracle_pair(depth, fmt, cam, radius, iterations, K_ROBUST, pixels=px)
     return compare(gs, o, tol, name, o_alt=oa)
 
 
@@ -155,3 +155,35 @@ def test_largest_batch(ctx):
         torch.cuda.synchronize()
         for k, v in o.items():
             assert np.array_equal(got[i][k], v.cpu().numpy(), equal_nan=True), (i, k)
+
+
+PRECISION_CASES = [(kind, r, fmt, noisy) for kind in ("vga", "hd") for r in (3, 7, 11)
+                   for fmt in ("u16", "f16") for noisy in (False, True)]
+
+
+@pytest.fixture(scope="module")
+def precision_scenes():
+    cams = {"vga": scenes.CAM_VGA, "hd": scenes.CAM_HD}
+    out = {}
+    for kind, cam in cams.items():
+        out[(kind, False)] = scenes.cluttered_scene(cam, seed_frame=21, config_index=3, noise=False, dropout=0.0)
+        out[(kind, True)] = scenes.cluttered_scene(cam, seed_frame=21, config_index=3)
+    return out
+
+
+@pytest.mark.parametrize("kind,r,fmt,noisy", PRECISION_CASES)
+def test_precision_form_grid(ctx, precision_scenes, kind, r, fmt, noisy):
+    """The precision form on full frames: 640x480 and 1280x720, r in {3, 7, 11}, uint16 mm
+    and FP16 m input, without and with sensor noise; k1/k2 on 600 sampled pixels against
+    the oracle (tolerance 1e-3: both inputs are quantised), and the share of pixels
+    recomputed in FP64 logged per case."""
+    from tests.helpers import gpu_fit
+    sc = precision_scenes[(kind, noisy)]
+    depth = sc.depth_u16() if fmt == "u16" else sc.depth_m.astype(np.float16)
+    log(f"[case] precision {kind} r={r} {fmt} {'noisy' if noisy else 'noiseless'}")
+    g = gpu_fit(ctx, depth, fmt, sc.camera, radius=r, iterations=5)
+    valid = int(np.sum((g["flags"] & 1) != 0))
+    st = _check_sampled(g, depth, sc.camera, r, 5, f"{kind} r={r} {fmt}", n=600, seed=300 + r, fmt=fmt)
+    log(f"[precision] {kind} {sc.camera.width}x{sc.camera.height} r={r} {fmt} "
+        f"{'noisy' if noisy else 'noiseless'}: max {st['max_err']:.2e} rms {st['rms_err']:.2e} "
+        f"recomputed {100.0 * g['refits'] / max(valid, 1):.1f} %")
