@@ -425,8 +425,10 @@ qc_status qc_tune(qc_context* ctx, const qc_frame* frame, const qc_params* param
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t a = nullptr, b = nullptr;
     if ((e = hipSetDevice(ctx->device)) != hipSuccess || (e = hipEventCreate(&a)) != hipSuccess ||
-        (e = hipEventCreate(&b)) != hipSuccess)
+        (e = hipEventCreate(&b)) != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
         return hip_fail(ctx, e);
+    }
     const bool timing = ctx->timing;
     ctx->timing = false;
     int best = 16;

@@ -268,6 +268,8 @@ qc_status qc_server_create(qc_context* ctx, const qc_server_config* cfg, qc_serv
     if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&s->compute[0], hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&s->compute[1], hipStreamNonBlocking) != hipSuccess) {
+        for (hipStream_t st : {s->copy_stream, s->compute[0], s->compute[1]})
+            if (st) (void)hipStreamDestroy(st);
         (void)hipFree(d);
         (void)hipHostFree(h);
         return QC_ERR_HIP;
