@@ -189,15 +189,21 @@ def measure_served(ctx, duration_s: float = 4.0, fps: float = 240.0, sensors: in
                 "p50_ms": round(float(np.percentile(lat, 50)), 3),
                 "p99_ms": round(float(np.percentile(lat, 99)), 3), "wall_s": round(span, 3)}
 
+    def progress(name, r):
+        print(f"[served trace] {fps:.0f} frames/s, {duration_s:.0f} s: {name} done "
+              f"(p50 {r['p50_ms']} ms, p99 {r['p99_ms']} ms)", file=sys.stderr, flush=True)
+        return r
+
     if warm_up:
         plain(False)   # warm-up of every radius variant
     res = {"trace": f"{sensors} sensors, Poisson arrivals {fps:.0f} frames/s aggregate over "
                     f"{duration_s:.0f} s (seeded), 512x424 ToF / 640x480 / 1280x720 u16, "
                     f"r in 3..11, T=5, {len(trace)} frames",
-           "served_realtime": served(True), "plain_realtime": plain(True)}
+           "served_realtime": progress("served realtime", served(True)),
+           "plain_realtime": progress("plain realtime", plain(True))}
     if saturated:
-        res["served_saturated"] = served(False)
-        res["plain_saturated"] = plain(False)
+        res["served_saturated"] = progress("served saturated", served(False))
+        res["plain_saturated"] = progress("plain saturated", plain(False))
     return res
 
 
@@ -447,6 +453,9 @@ def main() -> int:
     ap.add_argument("--no-reject", action="store_true")
     ap.add_argument("--no-paper-grid", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--trace-seconds", type=float, default=0.0,
+                    help="length of every served trace (default: 4 s at 240 frames/s, 3 s at "
+                         "the lower rates; the rates' traces are otherwise identical)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 10 plain device copies of BYTES bytes (calibrates the "
@@ -554,7 +563,7 @@ def main() -> int:
     if not args.no_batched and args.precision != "fp64":
         result["batched_form"] = measure_batched(ctx)
     if not args.no_served and args.precision != "fp64":
-        sv = measure_served(ctx)
+        sv = measure_served(ctx, duration_s=args.trace_seconds or 4.0)
         result["served_form"] = sv
         result["served_vs_plain"] = {
             "saturated_throughput_ratio": round(sv["served_saturated"]["pixels_per_s"] /
@@ -564,7 +573,8 @@ def main() -> int:
         # latency against load: the same sensors at lower aggregate rates
         sweep = []
         for fps in (30.0, 60.0, 120.0):
-            lv = measure_served(ctx, duration_s=3.0, fps=fps, saturated=False, warm_up=False)
+            lv = measure_served(ctx, duration_s=args.trace_seconds or 3.0, fps=fps, saturated=False,
+                                warm_up=False)
             sweep.append({"fps": fps, "frames": lv["served_realtime"]["frames"],
                           "served_p50_ms": lv["served_realtime"]["p50_ms"],
                           "served_p99_ms": lv["served_realtime"]["p99_ms"],

@@ -4,7 +4,8 @@
 //   submitted (depth copied into pinned staging by the caller's thread)
 //   -> admitted (device memory reserved from the budget, FIFO order; upload enqueued on
 //      a copy stream)
-//   -> ready (upload finished; staging returned)
+//   -> ready (upload enqueued: a batch may take the frame at once, its stream waiting for
+//      the upload on the device; the staging range returns when the upload is done)
 //   -> running (fitted by qc_fit_batch on one of two compute streams, at most
 //      max_in_flight batches at once, up to max_batch ready frames per batch)
 //   -> done (completion queued for qc_server_poll; device memory held until release).
@@ -43,6 +44,7 @@ struct Request {
     qc_request req{};           // depth points into pinned staging while queued
     size_t frame_bytes = 0;     // width * height * sample
     size_t stage_off = 0;
+    bool staged = false;        // holds its pinned staging range (until its upload is done)
     size_t dev_off = 0, dev_bytes = 0;
     int64_t t_submit = 0, t_done = 0;
     hipEvent_t uploaded = nullptr;
@@ -116,6 +118,11 @@ struct qc_server {
         if (cfg.outputs & QC_OUT_FLAGS) q->flags = reinterpret_cast<uint8_t*>(p);
     }
 
+    void unstage(Request* q) {
+        pin_alloc.release(q->stage_off, q->frame_bytes);
+        q->staged = false;
+    }
+
     void complete(Request* q, qc_status st) {
         q->status = st;
         q->t_done = now_ns();
@@ -144,22 +151,32 @@ struct qc_server {
                 complete(q, QC_ERR_HIP);
                 done_cv.notify_all();
             } else {
+                // the frame can join a batch at once: the batch's stream waits for the
+                // upload on the device; its staging range is released when it is done
+                q->staged = true;
                 uploading.push_back(q);
+                ready.push_back(q);
             }
             moved = true;
         }
-        // finished uploads
+        // finished uploads (in order on the copy stream): their staging can be reused
         while (!uploading.empty() && hipEventQuery(uploading.front()->uploaded) == hipSuccess) {
-            Request* q = uploading.front();
+            unstage(uploading.front());
             uploading.pop_front();
-            pin_alloc.release(q->stage_off, q->frame_bytes);
-            ready.push_back(q);
             moved = true;
         }
         // finished batches
         for (size_t i = 0; i < running.size();) {
             if (hipEventQuery(running[i].done) == hipSuccess) {
-                for (Request* q : running[i].reqs) complete(q, QC_OK);
+                // the batch waited for its frames' uploads: they are done, and a completed
+                // request (which its owner may release) must hold no staging
+                for (Request* q : running[i].reqs) {
+                    if (q->staged) {
+                        unstage(q);
+                        uploading.erase(std::find(uploading.begin(), uploading.end(), q));
+                    }
+                    complete(q, QC_OK);
+                }
                 (void)hipEventDestroy(running[i].done);
                 running.erase(running.begin() + static_cast<long>(i));
                 done_cv.notify_all();
@@ -196,7 +213,7 @@ struct qc_server {
             next_compute ^= 1;
             lk.unlock();
             hipError_t e = hipSuccess;
-            for (Request* q : b.reqs)   // already complete; orders the batch after its uploads
+            for (Request* q : b.reqs)   // orders the batch after its frames' uploads
                 if (e == hipSuccess) e = hipStreamWaitEvent(s, q->uploaded, 0);
             qc_status st = e == hipSuccess ? qc_fit_batch(ctx, items.data(), static_cast<int32_t>(items.size()), s)
                                            : QC_ERR_HIP;
@@ -207,7 +224,15 @@ struct qc_server {
             stats.batches += 1;
             if (st != QC_OK) {
                 if (b.done) (void)hipEventDestroy(b.done);
-                for (Request* q : b.reqs) complete(q, st);
+                for (Request* q : b.reqs) {
+                    if (q->staged) {
+                        // the copy engine may still read the staging: wait for it first
+                        (void)hipEventSynchronize(q->uploaded);
+                        unstage(q);
+                        uploading.erase(std::find(uploading.begin(), uploading.end(), q));
+                    }
+                    complete(q, st);
+                }
                 done_cv.notify_all();
             } else {
                 running.push_back(std::move(b));
@@ -374,7 +399,7 @@ qc_status qc_server_get_stats(qc_server* s, qc_server_stats* out) {
     if (!s || !out) return QC_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
     *out = s->stats;
-    out->queued = s->submitted.size() + s->uploading.size() + s->ready.size();
+    out->queued = s->submitted.size() + s->ready.size();
     out->device_bytes_in_use = s->dev_alloc.used();
     return QC_OK;
 }
