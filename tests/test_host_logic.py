@@ -16,3 +16,49 @@ def test_range_allocator_first_fit_and_coalescing(tmp_path):
                    check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
     assert out.strip() == "OK"
+
+
+def test_algorithmic_flop_count_matches_brute_force():
+    """bench.py prices the headline kernel by T (97 |S| + 250) + 14 |S_n| + 40 flops per
+    valid pixel, with |S|, |S_n| counted by summed-area tables; here the window counts
+    are recounted with plain loops (borders clipped) on a small random mask."""
+    import sys
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    rng = np.random.default_rng([1707_00385, 90])
+    d = (rng.random((17, 23)) > 0.3).astype(np.uint16) * 1000
+    H, W = d.shape
+    total = 0.0
+    for v in range(H):
+        for u in range(W):
+            if d[v, u] == 0:
+                continue
+            def count(r):
+                return sum(1 for dv in range(-r, r + 1) for du in range(-r, r + 1)
+                           if 0 <= v + dv < H and 0 <= u + du < W and d[v + dv, u + du] > 0)
+            total += bench.ITERS * (97.0 * count(bench.RADIUS) + 250.0) + 14.0 * count(bench.NRAD) + 40.0
+    assert bench.algorithmic_flops(d) == total
+
+
+def test_synthetic_workload_generators():
+    """The batched mix and the served trace are seeded, have the stated composition, and
+    the trace's arrivals are ordered, inside the duration and near the stated rate."""
+    import sys
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    from paper_1707_00385_amd import scenes
+    mix = scenes.batch_mix(64, seed=0)
+    assert mix == scenes.batch_mix(64, seed=0)
+    assert [m["kind"] for m in mix].count("hd") in (21, 22)
+    assert {m["radius"] for m in mix} <= {3, 5, 7, 11} and {m["iterations"] for m in mix} <= {3, 5}
+    tr = scenes.poisson_trace(6, 240.0, 20.0, seed=0)
+    assert tr == scenes.poisson_trace(6, 240.0, 20.0, seed=0)
+    t = np.array([e["t"] for e in tr])
+    assert np.all(np.diff(t) >= 0) and t[0] >= 0 and t[-1] < 20.0
+    assert abs(len(tr) - 4800) < 5 * np.sqrt(4800)   # Poisson count, 5 sigma
+    kinds = {}
+    for e in tr:
+        assert kinds.setdefault(e["sensor"], e["kind"]) == e["kind"]   # one resolution per sensor
+        assert 3 <= e["radius"] <= 11 and e["iterations"] == 5
+    assert len(kinds) == 6
