@@ -249,6 +249,30 @@ def measure_batched(ctx, reps: int = 5) -> dict:
                    "Kinect-like u16; r in {3,5,7,11}, T in {3,5}, seeded"}
 
 
+def measure_precision_modes(ctx, dev, K, steps: int = 100) -> dict:
+    """The headline frames in the other two precision modes: FP64 throughout (every pixel
+    fitted in double precision) and FP32 only (no recomputation, so unreliable pixels keep
+    their FP32 fit and flag) -- the cost of the precision form's choices."""
+    import torch
+    from paper_1707_00385_amd.api import make_outputs, make_params
+    out = make_outputs(HEIGHT, WIDTH, dev[0].device, flags=False)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        params = make_params(radius=RADIUS, iterations=ITERS, k=K_ROBUST, normal_radius=NRAD,
+                             precision=prec)
+        for i in range(10):
+            ctx.fit(dev[i % N_FRAMES], K, params=params, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ctx.fit(dev[i % N_FRAMES], K, params=params, out=out)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[prec] = {"ms_per_frame": round(1e3 * wall / steps, 4),
+                     "pixels_per_s": round(steps * WIDTH * HEIGHT / wall, 1)}
+    return res
+
+
 def measure_rejection(ctx, dev, K, precision: str, steps: int = 100) -> dict:
     """The rejection variant ("Ours+R": Eq. (11) with R = 2 MSE) on the headline frames:
     per-frame fits as in the headline measurement, plus its FP64 recomputation share."""
@@ -554,6 +578,8 @@ def main() -> int:
         "refit_fraction": round(float(np.mean(refits)) / (WIDTH * HEIGHT), 5),
         "roofline": roofline,
     }
+    if args.precision == "mixed":
+        result["precision_modes"] = measure_precision_modes(ctx, dev, K)
     if not args.no_reject:
         result["rejection_variant"] = measure_rejection(ctx, dev, K, args.precision)
     if not args.no_paper_grid and args.precision == "mixed":
