@@ -477,6 +477,7 @@ def main() -> int:
     ap.add_argument("--no-reject", action="store_true")
     ap.add_argument("--no-paper-grid", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-precision-modes", action="store_true")
     ap.add_argument("--trace-seconds", type=float, default=0.0,
                     help="length of every served trace (default: 4 s at 240 frames/s, 3 s at "
                          "the lower rates; the rates' traces are otherwise identical)")
@@ -578,7 +579,7 @@ def main() -> int:
         "refit_fraction": round(float(np.mean(refits)) / (WIDTH * HEIGHT), 5),
         "roofline": roofline,
     }
-    if args.precision == "mixed":
+    if args.precision == "mixed" and not args.no_precision_modes:
         result["precision_modes"] = measure_precision_modes(ctx, dev, K)
     if not args.no_reject:
         result["rejection_variant"] = measure_rejection(ctx, dev, K, args.precision)

@@ -116,7 +116,7 @@ typedef struct {
 typedef struct qc_context qc_context;
 
 /* Defaults: r = 7, r_n = 3, T = 5, k = 1e-5 m^2, reject = 0, depth_scale = 1e-3, MIXED,
- * cond_max = 30, step_max = 0.1, tile_width = 0, stride = 1. */
+ * cond_max = 15, step_max = 0.1, tile_width = 0, stride = 1. */
 void qc_params_default(qc_params* params);
 
 /* Creates a context bound to HIP device `device`.  *ctx receives the handle. */

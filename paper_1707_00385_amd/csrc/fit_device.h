@@ -399,13 +399,15 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         // FP32: the closest any decision e^2 < R came to the bound; a pixel with one too
         // close to be sure of is left to FP64
         Real gap = Real(INFINITY);
-        // Normal-equation sums (kSumA / kSumB).  The FP32 path sums each window row (2r+1
-        // terms) in FP32 and adds the row sums in FP64: one sequence of FP32 additions over
-        // the whole window (225 terms at r = 7) is the dominant rounding error of an FP32
-        // fit, while a row's error stays near that of the terms themselves; per neighbour
-        // this takes 26 FP32 FMAs instead of 7 conversions and 26 FP64 FMAs.  The FP64 path
-        // accumulates in FP64 throughout.
+        // Normal-equation sums (kSumA / kSumB).  The FP32 path sums each pair of window
+        // rows (2 (2r+1) terms) in FP32 and adds these partial sums in FP64: one sequence of
+        // FP32 additions over the whole window (225 terms at r = 7) is the dominant rounding
+        // error of an FP32 fit, while a row pair's error stays within a few times that of
+        // the terms themselves; per neighbour this takes 26 FP32 FMAs instead of 7
+        // conversions and 26 FP64 FMAs, and the 26 conversions and FP64 additions come
+        // once per two rows.  The FP64 path accumulates in FP64 throughout.
         constexpr bool row_sums = sizeof(Real) == 4;
+        bool pair_odd = false;   // a row of the current pair has been summed
         Acc sum[kSums];
         Real rsum[kSums];
 #pragma unroll
@@ -450,13 +452,22 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
             }
         }, [&]() {
             if constexpr (row_sums) {
+                if (pair_odd) {
 #pragma unroll
-                for (int k = 0; k < kSums; ++k) {
-                    sum[k] += Acc(rsum[k]);
-                    rsum[k] = 0;
+                    for (int k = 0; k < kSums; ++k) {
+                        sum[k] += Acc(rsum[k]);
+                        rsum[k] = 0;
+                    }
                 }
+                pair_odd = !pair_odd;
             }
         });
+        if constexpr (row_sums) {
+            if (pair_odd) {   // the last row, unpaired
+#pragma unroll
+                for (int k = 0; k < kSums; ++k) sum[k] += Acc(rsum[k]);
+            }
+        }
         if constexpr (REJ && sizeof(Real) == 4) near |= thresh < Real(INFINITY) && gap <= Real(kRejectMargin) * thresh;
         if constexpr (NP > 1) {
 #pragma unroll

@@ -18,7 +18,7 @@ hipError_t launch_frame_strided_reject(const FitDesc& d, const RefitList& list, 
 namespace {
 
 // FP32 pass over one frame: one 256-lane workgroup per tile (REJ: the rejection variant
-// of Eq. (11)).  Its unrolled rows with FP32 row sums need ~150 registers: 3 waves per
+// of Eq. (11)).  Its unrolled rows with FP32 sums per row pair need ~150 registers: 3 waves per
 // SIMD (the pass runs as fast at 2, 3 or 4 waves per SIMD).
 template <int R, bool REJ, bool STR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))

@@ -258,7 +258,7 @@ void qc_params_default(qc_params* p) {
     p->reject = 0;
     p->depth_scale = 1e-3f;
     p->precision = QC_PREC_MIXED;
-    p->cond_max = 30.f;
+    p->cond_max = 15.f;
     p->step_max = 1e-1f;
     p->tile_width = 0;
     p->stride = 1;

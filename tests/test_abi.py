@@ -36,6 +36,7 @@ def test_defaults_and_status_strings():
     assert (p.radius, p.normal_radius, p.iterations) == (7, 3, 5)
     assert p.k == pytest.approx(1e-5) and p.depth_scale == pytest.approx(1e-3)
     assert p.precision == _lib.QC_PREC_MIXED and p.reject == 0 and p.stride == 1
+    assert p.cond_max == pytest.approx(15.0) and p.step_max == pytest.approx(0.1)
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.qc_status_string(code)
     assert lib.qc_status_string(12345) == b"unknown status"
