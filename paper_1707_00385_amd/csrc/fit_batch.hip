@@ -48,13 +48,13 @@ void refit_batch_f64(const FitDesc* frames, RefitList list) {
     for (;;) {
         const uint32_t base = next_ranks(&list.counts[3]);
         if (base >= ranks) break;
-        const uint32_t slot = entry_of(list, base);
-        const uint32_t entry = __builtin_amdgcn_readfirstlane(list.entries[slot]);
-        const int t = listed_thread(list.masks + 4 * static_cast<size_t>(slot),
-                                    static_cast<int>(base - list.ranks[slot] + threadIdx.x / kRefitLanes));
-        const FitDesc d = frames[entry >> 24];
+        const Chunk ck = chunk_at(list, base);
+        const uint64_t* m = list.masks + 4 * static_cast<size_t>(ck.slot);
+        const uint64_t w[4] = {m[0], m[1], m[2], m[3]};
+        const FitDesc d = frames[ck.entry >> 24];
         with_radius(d.radius, [&](auto rc) {
-            refit_chunk<decltype(rc)::value>(d, entry & 0xffffffu, t, grp, region);
+            refit_chunk<decltype(rc)::value>(d, ck.entry & 0xffffffu, w,
+                                             static_cast<int>(ck.first + threadIdx.x / kRefitLanes), grp, region);
         });
     }
 }

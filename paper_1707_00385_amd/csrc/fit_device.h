@@ -810,10 +810,9 @@ __device__ __forceinline__ void fit_tile_body(const FitDesc& d, int tx, int ty, 
                         reinterpret_cast<unsigned long long*>(list.counts), (1ull << 32) | padded);
                     atomicAdd(&list.counts[4], n);
                     const uint32_t slot = static_cast<uint32_t>(old >> 32);
-                    list.entries[slot] = (frame << 24) | static_cast<uint32_t>(ty * tiles_across(d) + tx);
-                    list.ranks[slot] = static_cast<uint32_t>(old);
+                    const uint64_t entry = (frame << 24) | static_cast<uint32_t>(ty * tiles_across(d) + tx);
                     for (uint32_t c = 0; c < padded / kChunk; ++c)
-                        list.chunks[static_cast<uint32_t>(old) / kChunk + c] = slot;
+                        list.chunks[static_cast<uint32_t>(old) / kChunk + c] = (entry << 32) | (slot << 8) | c;
 #pragma unroll
                     for (int w = 0; w < 4; ++w) list.masks[4 * slot + w] = m[w];
                 }
@@ -856,17 +855,22 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
     return pos;
 }
 
-// The entry holding the chunk of ranks that starts at `base` (a multiple of kChunk below
-// counts[0]), the same in every lane.
-__device__ __forceinline__ uint32_t entry_of(const RefitList& list, uint32_t base) {
-    return __builtin_amdgcn_readfirstlane(list.chunks[base / kChunk]);
+// The chunk of ranks that starts at `base` (a multiple of kChunk below counts[0]), the
+// same in every lane: its entry ((frame << 24) | tile), the entry's slot in the masks, and
+// the number of listed pixels of the entry before the chunk.
+struct Chunk {
+    uint32_t entry, slot, first;
+};
+__device__ __forceinline__ Chunk chunk_at(const RefitList& list, uint32_t base) {
+    const uint64_t rec = list.chunks[base / kChunk];
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(rec));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(rec >> 32));
+    return Chunk{hi, lo >> 8, (lo & 0xffu) * kChunk};
 }
 
-// Thread (pixel of the tile) of the n-th listed pixel of an entry's 256-bit mask m, or -1
-// when the entry lists no more than n pixels.
-__device__ __forceinline__ int listed_thread(const uint64_t* m, int n) {
-    // all four words are read up front (one memory round trip)
-    const uint64_t w0 = m[0], w1 = m[1], w2 = m[2], w3 = m[3];
+// Thread (pixel of the tile) of the n-th listed pixel of an entry's 256-bit mask
+// (w0, w1, w2, w3), or -1 when the entry lists no more than n pixels.
+__device__ __forceinline__ int listed_thread(uint64_t w0, uint64_t w1, uint64_t w2, uint64_t w3, int n) {
     const int c0 = __popcll(w0), c1 = c0 + __popcll(w1), c2 = c1 + __popcll(w2);
     const int c3 = c2 + __popcll(w3);
     if (n >= c3) return -1;
@@ -886,10 +890,10 @@ __device__ __forceinline__ uint32_t next_ranks(uint32_t* counter) {
 // FP64 recomputation of one chunk of a batch: the chunk lies in one entry, hence in one
 // tile of one frame, so the frame's descriptor and window radius are uniform across the
 // wave.  The wave stages that tile plus halo in its LDS `region` (sized by the host for
-// the largest region of the batch) and fits its pixels from there, `thread` being the
-// listed pixel's thread in the tile (-1 for the lanes of a part-filled chunk).
+// the largest region of the batch) and fits its pixels from there: this lane's pixel is
+// the n-th listed in the entry's mask w (none for the lanes of a part-filled chunk).
 template <int R>
-__device__ __forceinline__ void refit_chunk(const FitDesc& d, uint32_t tile, int thread,
+__device__ __forceinline__ void refit_chunk(const FitDesc& d, uint32_t tile, const uint64_t (&w)[4], int n,
                                             const LaneGroup<kRefitLanes>& grp, float2* region) {
     const int tw = d.tile_w, th = 256 / tw;
     const int across = tiles_across(d);
@@ -897,6 +901,7 @@ __device__ __forceinline__ void refit_chunk(const FitDesc& d, uint32_t tile, int
     const int halo = max(R, d.normal_radius);
     const int pitch = tw + 2 * halo;
     stage_region_wave(d, region, bx - halo, by - halo, pitch, th + 2 * halo);
+    const int thread = listed_thread(w[0], w[1], w[2], w[3], n);
     if (thread >= 0) {
         const int lx = thread % tw, ly = thread / tw;
         const float2* centre = region + (ly + halo) * pitch + (lx + halo);

@@ -55,12 +55,14 @@ void refit_f64(FitDesc d, RefitList list) {
     for (;;) {
         const uint32_t base = next_ranks(&list.counts[3]);
         if (base >= ranks) break;
-        const uint32_t slot = entry_of(list, base);
-        const uint32_t tile = list.entries[slot] & 0xffffffu;
+        const Chunk ck = chunk_at(list, base);
+        // the entry's mask is read before the tile is staged: both reads are in flight together
+        const uint64_t* m = list.masks + 4 * static_cast<size_t>(ck.slot);
+        const uint64_t w0 = m[0], w1 = m[1], w2 = m[2], w3 = m[3];
+        const uint32_t tile = ck.entry & 0xffffffu;
         const int bx = static_cast<int>(tile % across) * tw, by = static_cast<int>(tile / across) * th;
         stage_region_wave(d, region, bx - halo, by - halo, pitch, th + 2 * halo);
-        const int t = listed_thread(list.masks + 4 * static_cast<size_t>(slot),
-                                    static_cast<int>(base - list.ranks[slot] + threadIdx.x / kRefitLanes));
+        const int t = listed_thread(w0, w1, w2, w3, static_cast<int>(ck.first + threadIdx.x / kRefitLanes));
         if (t >= 0) {
             const int lx = t % tw, ly = t / tw;
             const float2* centre = region + (ly + halo) * pitch + (lx + halo);

@@ -15,16 +15,13 @@ bool valid_tile_width(int tile_w) {
 
 // A tile lists at most 256 pixels, i.e. 256 / kChunk = 16 chunks.
 size_t refit_list_bytes(int64_t tiles) {
-    return static_cast<size_t>(tiles) * (4 * sizeof(uint64_t) + (2 + 256 / kChunk) * sizeof(uint32_t));
+    return static_cast<size_t>(tiles) * (4 + 256 / kChunk) * sizeof(uint64_t);
 }
 
 RefitList refit_list(void* storage, int64_t tiles, uint32_t* counts) {
-    char* p = static_cast<char*>(storage);
     RefitList l;
-    l.masks = reinterpret_cast<uint64_t*>(p);
-    l.entries = reinterpret_cast<uint32_t*>(p + 4 * sizeof(uint64_t) * static_cast<size_t>(tiles));
-    l.ranks = l.entries + tiles;
-    l.chunks = l.ranks + tiles;
+    l.masks = static_cast<uint64_t*>(storage);
+    l.chunks = l.masks + 4 * static_cast<size_t>(tiles);
     l.counts = counts;
     return l;
 }

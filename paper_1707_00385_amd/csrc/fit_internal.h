@@ -32,10 +32,11 @@ struct FitDesc {
 // FP32 pass appends one entry per tile holding such pixels; the FP64 pass takes the
 // listed pixels by rank, so its work does not depend on how they cluster in tiles.
 struct RefitList {
-    uint32_t* entries;   // per entry: (frame << 24) | tile index within the frame
-    uint32_t* ranks;     // per entry: number of pixels listed in the entries before it
     uint64_t* masks;     // 4 words per entry: the listed pixels (bit t = thread t of the tile)
-    uint32_t* chunks;    // per 16 ranks (16 per entry at most): the entry holding them
+    uint64_t* chunks;    // per 16 ranks (16 per entry at most), all the FP64 pass needs to
+                         // start on them: (entry << 32) | (slot << 8) | c, with entry =
+                         // (frame << 24) | tile index within the frame, slot the entry's
+                         // index in `masks`, c the chunk's index within the entry
     uint32_t* counts;    // kCountWords words, 8-byte aligned, zeroed by every launch:
                          // [0] ranks handed out (each entry's pixel count rounded up to a
                          // multiple of 16, so that 16 consecutive ranks never span two
@@ -45,7 +46,7 @@ struct RefitList {
 };
 constexpr int kCountWords = 8;
 
-// Bytes of entries + ranks + masks + chunk table for `tiles` entries, and the list carved
+// Bytes of the masks and the chunk table for `tiles` entries, and the list carved
 // out of them.
 size_t refit_list_bytes(int64_t tiles);
 RefitList refit_list(void* storage, int64_t tiles, uint32_t* counts);
