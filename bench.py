@@ -33,11 +33,37 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1707_00385_amd", "csrc", f)
                   for f in ("fit_device.h", "fit_frame.h", "fit_frame.hip", "fit_internal.h")]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank-line / trailing-space differences, so that a
+    comment edit does not count as a change of the kernel."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif text[i] in "\"'":
+            q, j = text[i], i + 1
+            while j < n and text[j] != q:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(text[i])
+            i += 1
+    lines = [line.rstrip() for line in "".join(out).split("\n")]
+    return "\n".join(line for line in lines if line)
+
+
 def kernel_source_hash() -> str:
+    """Hash of the FP32 kernel's code (comments excluded): the stored HBM traffic is used
+    only while it matches."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -756,7 +756,7 @@ __device__ __forceinline__ int tiles_across(const FitDesc& d) {
 // One tile of tw x (blockDim.x / tw) pixels, halo staged in LDS, one lane per pixel.  In
 // MIXED precision the pixels whose FP32 fit is unreliable are not stored but listed: one
 // list entry for the tile with a 256-bit mask of them (bit t = thread t = pixel
-// (t % tw, t / tw)) and the rank of its first listed pixel.
+// (t % tw, t / tw)), and one record per 16 of its ranks naming the entry.
 template <typename Real, int R, bool REJ = false, bool STR = false>
 __device__ __forceinline__ void fit_tile_body(const FitDesc& d, int tx, int ty, uint32_t frame,
                                               const RefitList& list) {
