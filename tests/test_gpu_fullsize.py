@@ -32,12 +32,13 @@ def _sample(depth, n, seed):
     return np.sort(rng.choice(idx, size=min(n, idx.size), replace=False))
 
 
-def _check_sampled(g, depth, cam, radius, iterations, name, n=800, seed=0, tol=1e-3, fmt="u16"):
+def _check_sampled(g, depth, cam, radius, iterations, name, n=800, seed=0, tol=1e-3, fmt="u16",
+                   max_nonunique=0.01):
     px = _sample(depth, n, seed)
     gs = {k: (v.reshape(-1, 3)[px] if k == "normal" else v.reshape(-1)[px])
           for k, v in g.items() if isinstance(v, np.ndarray)}
     o, oa = oracle_pair(depth, fmt, cam, radius, iterations, K_ROBUST, pixels=px)
-    return compare(gs, o, tol, name, o_alt=oa)
+    return compare(gs, o, tol, name, o_alt=oa, max_nonunique=max_nonunique)
 
 
 def _sensor_pool():
@@ -187,3 +188,18 @@ def test_precision_form_grid(ctx, precision_scenes, kind, r, fmt, noisy):
     log(f"[precision] {kind} {sc.camera.width}x{sc.camera.height} r={r} {fmt} "
         f"{'noisy' if noisy else 'noiseless'}: max {st['max_err']:.2e} rms {st['rms_err']:.2e} "
         f"recomputed {100.0 * g['refits'] / max(valid, 1):.1f} %")
+
+
+def test_fp64_mode_on_the_headline_frame(ctx):
+    """FP64 mode (every pixel fitted in double precision) on a full 640x480 u16 headline
+    frame, sampled pixels against the oracle at 2e-7 (its outputs are FP32).  At this
+    tolerance the uniqueness probe asks the oracle to move by less than 2e-9 under
+    rounding-level perturbations of the depth, which about 2 % of a noisy frame's pixels do
+    not (the iteration amplifies them); those are counted, at most 5 %."""
+    from tests.helpers import gpu_fit
+    sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=2, config_index=1)
+    d = sc.depth_u16()
+    log("[case] 640x480 u16 r=7 FP64 mode")
+    g = gpu_fit(ctx, d, "u16", sc.camera, radius=7, iterations=5, precision="fp64")
+    assert np.all((g["flags"][(g["flags"] & 1) != 0] & 2) != 0)   # every valid pixel fitted in FP64
+    _check_sampled(g, d, sc.camera, 7, 5, "vga fp64 mode", n=800, seed=11, tol=2e-7, max_nonunique=0.05)
