@@ -34,7 +34,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1707_00385_amd", "csrc", f)
 
 
 def _code_only(text: str) -> str:
-    """C++ source without comments and blank-line / trailing-space differences, so that a
+    """C++ source without comments, blank lines and differences in spacing, so that a
     comment edit does not count as a change of the kernel."""
     out, i, n = [], 0, len(text)
     while i < n:
@@ -53,7 +53,7 @@ def _code_only(text: str) -> str:
         else:
             out.append(text[i])
             i += 1
-    lines = [line.rstrip() for line in "".join(out).split("\n")]
+    lines = [" ".join(line.split()) for line in "".join(out).split("\n")]
     return "\n".join(line for line in lines if line)
 
 

@@ -62,3 +62,17 @@ def test_synthetic_workload_generators():
         assert kinds.setdefault(e["sensor"], e["kind"]) == e["kind"]   # one resolution per sensor
         assert 3 <= e["radius"] <= 11 and e["iterations"] == 5
     assert len(kinds) == 6
+
+
+def test_traffic_record_key_ignores_comments_only():
+    """bench.py reuses the stored HBM traffic of the FP32 kernel only while the kernel's
+    code is unchanged: comment and blank-line edits keep the key, code edits change it."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    src = 'int f(int a) {  // twice\n    /* the value */ return 2 * a;\n}\nconst char* s = "// kept";\n'
+    same = '// header\nint f(int a) {\n\n    return 2 * a;   /* doubled */\n}\nconst char* s = "// kept";\n'
+    other = src.replace("2 * a", "3 * a")
+    assert bench._code_only(src) == bench._code_only(same)
+    assert bench._code_only(src) != bench._code_only(other)
+    assert '"// kept"' in bench._code_only(src)
