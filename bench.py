@@ -514,7 +514,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the fit shards by frame with no inter-GPU traffic, "
-              f"and this build runs on one GPU only (asked for --gpus {args.gpus}).",
+              f"and several GPUs are not measured by this script (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         return 2
 

@@ -38,7 +38,7 @@ extern "C" {
 typedef enum {
     QC_OK = 0,
     QC_ERR_INVALID_ARG = -1,   /* a pointer, size or parameter is out of range */
-    QC_ERR_UNSUPPORTED = -2,   /* a valid request this build does not implement */
+    QC_ERR_UNSUPPORTED = -2,   /* a valid request the library does not implement */
     QC_ERR_OOM = -3,           /* device scratch could not be allocated */
     QC_ERR_HIP = -4,           /* a HIP runtime call failed (see qc_last_hip_error) */
     QC_ERR_BUSY = -5,          /* the request cannot be admitted now; retry later */
