@@ -177,10 +177,11 @@ struct LaneGroup {
     }
 };
 
-// Loops over this lane's window rows; RC > 0 fixes R at compile time.  A row is fully
-// unrolled for FP32 (U = 0); FP64 unrolls it U neighbours at a time (U >= 2), so that the
-// dependency chains of several neighbours interleave, or keeps it rolled (U = 1), to stay
-// within the register file.
+// Loops over this lane's window rows, calling row_end() after each row -- after each pair
+// of rows for FP32; RC > 0 fixes R at compile time.  A row is fully unrolled for FP32
+// (U = 0); FP64 unrolls it U neighbours at a time (U >= 2), so that the dependency chains
+// of several neighbours interleave, or keeps it rolled (U = 1), to stay within the
+// register file.
 struct NoRowEnd {
     __device__ __forceinline__ void operator()() const {}
 };
@@ -193,11 +194,19 @@ __device__ __forceinline__ void for_window(const Src& src, int radius, const Lan
     // The row loop stays rolled: unrolled, a short body (e.g. the mean of e^2 ahead of the
     // accumulation) would keep a whole window of samples live across the two passes.
     if constexpr (RC > 0 && U == 0) {
+        // two rows per step, row_end() after each pair (and after a last, unpaired row)
 #pragma unroll 1
-        for (int dv = first; dv <= r; dv += NP) {
-            auto row = src.row(dv);
+        for (int dv = first; dv <= r; dv += 2 * NP) {
+            {
+                auto row = src.row(dv);
 #pragma unroll
-            for (int du = -RC; du <= RC; ++du) f(row[du], du, dv);
+                for (int du = -RC; du <= RC; ++du) f(row[du], du, dv);
+            }
+            if (dv + NP <= r) {
+                auto row = src.row(dv + NP);
+#pragma unroll
+                for (int du = -RC; du <= RC; ++du) f(row[du], du, dv + NP);
+            }
             row_end();
         }
     } else if constexpr (U >= 2) {
@@ -407,7 +416,6 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         // conversions and 26 FP64 FMAs, and the 26 conversions and FP64 additions come
         // once per two rows.  The FP64 path accumulates in FP64 throughout.
         constexpr bool row_sums = sizeof(Real) == 4;
-        bool pair_odd = false;   // a row of the current pair has been summed
         Acc sum[kSums];
         Real rsum[kSums];
 #pragma unroll
@@ -451,23 +459,16 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
                 for (int k = 0; k < kSums; ++k) sum[k] = fmaT(va[kSumA[k]], va[kSumB[k]], sum[k]);
             }
         }, [&]() {
+            // FP32: called after every pair of rows (the FP32 window loop takes two rows
+            // per step); FP64: after every row, with nothing to flush
             if constexpr (row_sums) {
-                if (pair_odd) {
 #pragma unroll
-                    for (int k = 0; k < kSums; ++k) {
-                        sum[k] += Acc(rsum[k]);
-                        rsum[k] = 0;
-                    }
+                for (int k = 0; k < kSums; ++k) {
+                    sum[k] += Acc(rsum[k]);
+                    rsum[k] = 0;
                 }
-                pair_odd = !pair_odd;
             }
         });
-        if constexpr (row_sums) {
-            if (pair_odd) {   // the last row, unpaired
-#pragma unroll
-                for (int k = 0; k < kSums; ++k) sum[k] += Acc(rsum[k]);
-            }
-        }
         if constexpr (REJ && sizeof(Real) == 4) near |= thresh < Real(INFINITY) && gap <= Real(kRejectMargin) * thresh;
         if constexpr (NP > 1) {
 #pragma unroll
