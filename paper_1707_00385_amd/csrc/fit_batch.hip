@@ -45,9 +45,7 @@ void refit_batch_f64(const FitDesc* frames, RefitList list) {
     extern __shared__ float2 region[];
     const uint32_t ranks = list.counts[0];
     const LaneGroup<kRefitLanes> grp{static_cast<int>(threadIdx.x % kRefitLanes)};
-    for (;;) {
-        const uint32_t base = next_ranks(&list.counts[3]);
-        if (base >= ranks) break;
+    for (uint32_t base = first_ranks(); base < ranks; base = next_ranks(&list.counts[3])) {
         const Chunk ck = chunk_at(list, base);
         const uint64_t* m = list.masks + 4 * static_cast<size_t>(ck.slot);
         const uint64_t w[4] = {m[0], m[1], m[2], m[3]};
@@ -77,8 +75,15 @@ size_t batch_refit_lds_bytes(const FitDesc& d) {
 }
 
 hipError_t launch_fit_batch(const FitDesc* frames, const uint32_t* first_tile,
-                            const uint32_t* header, int workgroups, size_t refit_lds,
+                            const uint32_t* header, int cus, size_t refit_lds,
                             const RefitList& list, hipStream_t stream, hipEvent_t* events) {
+    const int workgroups = 4 * cus;   // FP32 pass: four 256-lane workgroups per CU requested
+    // FP64 pass: as many one-wave workgroups as can be resident at once (each starts on
+    // its own first chunk)
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refit_batch_f64, 64, refit_lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
     hipError_t e;
     hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, list.counts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -88,7 +93,7 @@ hipError_t launch_fit_batch(const FitDesc* frames, const uint32_t* first_tile,
                        header, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (events && (e = hipEventRecord(events[1], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(refit_batch_f64, dim3(4 * workgroups), dim3(64), refit_lds, stream, frames, list);
+    hipLaunchKernelGGL(refit_batch_f64, dim3(per_cu * cus), dim3(64), refit_lds, stream, frames, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (events && (e = hipEventRecord(events[2], stream)) != hipSuccess) return e;
     return hipSuccess;

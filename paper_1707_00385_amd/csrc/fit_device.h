@@ -881,11 +881,15 @@ __device__ __forceinline__ int listed_thread(uint64_t w0, uint64_t w1, uint64_t 
     return 192 + nth_set_bit(w3, n - c2);
 }
 
-// The next kChunk ranks for this wave (the same value in every lane).
+// Ranks of the FP64 passes, whose workgroups are one wave each: the first kChunk ranks
+// of wave b are b kChunk (no atomic at the start, where the whole grid asking one counter
+// at once would queue behind it); each later chunk is the next kChunk ranks after the
+// first round, counted by `counter` (the same value in every lane).
+__device__ __forceinline__ uint32_t first_ranks() { return blockIdx.x * kChunk; }
 __device__ __forceinline__ uint32_t next_ranks(uint32_t* counter) {
     uint32_t base = 0;
     if ((threadIdx.x % 64) == 0) base = atomicAdd(counter, kChunk);
-    return __builtin_amdgcn_readfirstlane(base);
+    return __builtin_amdgcn_readfirstlane(base) + gridDim.x * kChunk;
 }
 
 // FP64 recomputation of one chunk of a batch: the chunk lies in one entry, hence in one

@@ -4,6 +4,8 @@
 // instantiates one (REJ, STR) variant.
 #pragma once
 
+#include <atomic>
+
 #include "fit_device.h"
 
 namespace qc {
@@ -52,9 +54,7 @@ void refit_f64(FitDesc d, RefitList list) {
     const int pitch = tw + 2 * halo;
     const int across = tiles_across(d);
     const LaneGroup<kRefitLanes> grp{static_cast<int>(threadIdx.x % kRefitLanes)};
-    for (;;) {
-        const uint32_t base = next_ranks(&list.counts[3]);
-        if (base >= ranks) break;
+    for (uint32_t base = first_ranks(); base < ranks; base = next_ranks(&list.counts[3])) {
         const Chunk ck = chunk_at(list, base);
         // the entry's mask is read before the tile is staged: both reads are in flight together
         const uint64_t* m = list.masks + 4 * static_cast<size_t>(ck.slot);
@@ -80,6 +80,22 @@ void refit_f64(FitDesc d, RefitList list) {
         }
         __syncthreads();   // the next chunk re-stages the region
     }
+}
+
+// Grid of a persistent one-wave FP64 pass: as many workgroups as can be resident at once
+// with `lds` bytes each, so that every wave starts on its own first chunk (a workgroup
+// waiting for a slot would hold its first chunk back until the others have drained the
+// counter).  Any grid is correct; this one is cached per kernel for the last LDS size.
+template <auto Kernel>
+int resident_waves(size_t lds, int cus) {
+    static std::atomic<uint64_t> cache{~uint64_t{0}};   // (lds << 32) | workgroups per CU
+    const uint64_t c = cache.load(std::memory_order_relaxed);
+    int n = static_cast<int>(c & 0xffffffffu);
+    if ((c >> 32) != lds) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, Kernel, 64, lds) != hipSuccess || n < 1) n = 1;
+        cache.store((static_cast<uint64_t>(lds) << 32) | static_cast<uint32_t>(n), std::memory_order_relaxed);
+    }
+    return n * cus;
 }
 
 template <int R, bool REJ, bool STR>
@@ -108,7 +124,8 @@ hipError_t launch_variant(const FitDesc& d, const RefitList& list, int cus, hipS
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
     if (d.precision == 0) {
-        hipLaunchKernelGGL((refit_f64<R, REJ, STR>), dim3(16 * cus), dim3(64), lds, st, d, list);
+        hipLaunchKernelGGL((refit_f64<R, REJ, STR>), dim3(resident_waves<refit_f64<R, REJ, STR>>(lds, cus)),
+                           dim3(64), lds, st, d, list);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;

@@ -219,7 +219,7 @@ qc_status prepare_slot(qc_context* ctx, BatchSlot& s, int64_t entries, size_t re
         return hip_fail(ctx, e);
     hipError_t le = hipMemcpyAsync(s.dev, s.host, sizeof(BatchStaging), hipMemcpyHostToDevice, cs);
     if (le == hipSuccess)
-        le = qc::launch_fit_batch(s.dev->frames, s.dev->first_tile, s.dev->header, 4 * ctx->cus,
+        le = qc::launch_fit_batch(s.dev->frames, s.dev->first_tile, s.dev->header, ctx->cus,
                                   s.refit_lds, qc::refit_list(s.list, s.capacity, s.counts), cs);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
@@ -401,7 +401,7 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
             if ((e = hipEventCreate(&x)) != hipSuccess) return hip_fail(ctx, e);
         ctx->pending.insert(ctx->pending.end(), ev, ev + 3);
         if ((e = hipMemcpyAsync(s.dev, s.host, sizeof(BatchStaging), hipMemcpyHostToDevice, hs)) != hipSuccess ||
-            (e = qc::launch_fit_batch(s.dev->frames, s.dev->first_tile, s.dev->header, 4 * ctx->cus,
+            (e = qc::launch_fit_batch(s.dev->frames, s.dev->first_tile, s.dev->header, ctx->cus,
                                       s.refit_lds, qc::refit_list(s.list, s.capacity, s.counts), hs,
                                       ev)) != hipSuccess)
             return hip_fail(ctx, e);
