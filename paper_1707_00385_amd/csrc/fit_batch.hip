@@ -7,8 +7,10 @@ namespace {
 
 // Persistent FP32 pass over a batch of frames.  Tiles are numbered frame after frame
 // (frames ordered by the host from most to least work per tile; first_tile[f] is the
-// number of the frame's first tile, first_tile[n] the total); every workgroup takes the
-// next tile number from counts[2] until none is left, so all frames share one launch.
+// number of the frame's first tile, first_tile[n] the total).  Workgroup b starts on tile
+// b (the grid is the resident capacity, so no atomic is asked by the whole grid at once)
+// and then takes the next tile number beyond the first round from counts[2] until none is
+// left, so all frames share one launch.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))
 void fit_batch_f32(const FitDesc* frames, const uint32_t* first_tile, const uint32_t* header,
                    RefitList list) {
@@ -16,12 +18,7 @@ void fit_batch_f32(const FitDesc* frames, const uint32_t* first_tile, const uint
     const uint32_t nf = header[0];
     if (nf == 0) return;
     const uint32_t total = first_tile[nf];
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(&list.counts[2], 1u);
-        __syncthreads();
-        const uint32_t t = __builtin_amdgcn_readfirstlane(next);
-        __syncthreads();
-        if (t >= total) break;
+    for (uint32_t t = blockIdx.x; t < total;) {
         uint32_t lo = 0, hi = nf - 1;   // the frame holding tile t
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1) / 2;
@@ -34,7 +31,10 @@ void fit_batch_f32(const FitDesc* frames, const uint32_t* first_tile, const uint
         with_radius(d.radius, [&](auto rc) {
             fit_tile_body<float, decltype(rc)::value>(d, local % across, local / across, lo, list);
         });
-        __syncthreads();   // the next tile re-stages LDS
+        if (threadIdx.x == 0) next = atomicAdd(&list.counts[2], 1u) + gridDim.x;
+        __syncthreads();   // `next` is written, and the next tile may re-stage LDS
+        t = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();   // every lane has read `next` before thread 0 writes it again
     }
 }
 
@@ -77,23 +77,25 @@ size_t batch_refit_lds_bytes(const FitDesc& d) {
 hipError_t launch_fit_batch(const FitDesc* frames, const uint32_t* first_tile,
                             const uint32_t* header, int cus, size_t refit_lds,
                             const RefitList& list, hipStream_t stream, hipEvent_t* events) {
-    const int workgroups = 4 * cus;   // FP32 pass: four 256-lane workgroups per CU requested
-    // FP64 pass: as many one-wave workgroups as can be resident at once (each starts on
-    // its own first chunk)
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refit_batch_f64, 64, refit_lds) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
+    // both passes: as many workgroups as can be resident at once, each starting on its own
+    // first tile / chunk
+    const size_t lds = batch_lds_bytes();
+    int f32_per_cu = 0, f64_per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&f32_per_cu, fit_batch_f32, 256, lds) != hipSuccess ||
+        f32_per_cu < 1)
+        f32_per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&f64_per_cu, refit_batch_f64, 64, refit_lds) != hipSuccess ||
+        f64_per_cu < 1)
+        f64_per_cu = 1;
     hipError_t e;
     hipLaunchKernelGGL(zero_counts, dim3(1), dim3(64), 0, stream, list.counts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const size_t lds = batch_lds_bytes();
     if (events && (e = hipEventRecord(events[0], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(fit_batch_f32, dim3(workgroups), dim3(256), lds, stream, frames, first_tile,
+    hipLaunchKernelGGL(fit_batch_f32, dim3(f32_per_cu * cus), dim3(256), lds, stream, frames, first_tile,
                        header, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (events && (e = hipEventRecord(events[1], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(refit_batch_f64, dim3(per_cu * cus), dim3(64), refit_lds, stream, frames, list);
+    hipLaunchKernelGGL(refit_batch_f64, dim3(f64_per_cu * cus), dim3(64), refit_lds, stream, frames, list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (events && (e = hipEventRecord(events[2], stream)) != hipSuccess) return e;
     return hipSuccess;

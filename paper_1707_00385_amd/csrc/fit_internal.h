@@ -68,7 +68,7 @@ bool valid_tile_width(int tile_w);
 // ordered by decreasing work per tile), `first_tile` (device, n + 1 prefix sums of the
 // frames' tile counts), `header` (device: [0] = n frames), all read when the kernels run,
 // so the same launches can be captured once and replayed with new contents.  One
-// persistent FP32 pass of 4 workgroups per compute unit (`cus`) over all tiles, then one persistent FP64
+// persistent FP32 pass over all tiles, then one persistent FP64
 // pass over the listed pixels of all frames.  List capacity: first_tile[n] entries; at
 // most 256 frames.
 // `refit_lds`: dynamic LDS of the FP64 pass's one-wave workgroups, at least the largest
