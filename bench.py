@@ -115,9 +115,31 @@ def cpu_baseline(frame: np.ndarray, cam, budget_s: float = 10.0) -> dict:
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
+    # one thread on a band of the same frame (its rows plus the window's halo)
+    r0, r1 = HEIGHT // 2 - 40, HEIGHT // 2 + 40
+    band = np.ascontiguousarray(d[r0 - RADIUS:r1 + RADIUS])
+    t1 = time.perf_counter()
+    oracle.fit_image(band, cam.fx, cam.fy, cam.cx, cam.cy - (r0 - RADIUS), radius=RADIUS,
+                     iterations=ITERS, k=K_ROBUST, normal_radius=NRAD, threads=1)
+    el1 = time.perf_counter() - t1
     return {"value": runs * WIDTH * HEIGHT / el, "unit": "pixels/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{runs} full 640x480 u16 frames (r=7, T=5), FP64 C + OpenMP, {el:.1f} s"}
+            "sample": f"{runs} full 640x480 u16 frames (r=7, T=5), FP64 C + OpenMP, {el:.1f} s",
+            "one_core": {"value": band.size / el1, "unit": "pixels/s",
+                         "sample": f"rows {r0 - RADIUS}..{r1 + RADIUS - 1} of the first frame, "
+                                   f"1 thread, {el1:.2f} s"},
+            "host_cpu": _cpu_model()}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 _POOL = {}
