@@ -217,3 +217,39 @@ def test_batches_needing_more_lds_recapture():
                 _equal({k: v.cpu().numpy() for k, v in o.items()}, single, f"batch {step} frame {i}")
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("fmt", ["u16", "f16", "f32"])
+def test_pitched_rows_equal_dense_rows(ctx, fmt):
+    """A frame whose rows lie `pitch_bytes` apart, with padding between them, gives the
+    outputs of the same frame stored densely: per frame in MIXED and FP64 precision, and
+    inside a batch.  The padding (an odd number of samples, so the pitch is not a multiple
+    of four bytes for u16) holds valid depth, so a read past the last column would change
+    the right-hand border pixels."""
+    import torch
+    from paper_1707_00385_amd.api import make_params, upload_depth
+    cam = scenes.Camera(90, 70, 80.0, 80.0, 44.5, 34.5)
+    sc = scenes.cluttered_scene(cam, seed_frame=11, config_index=8)
+    dense = upload_depth(sc.depth_u16() if fmt == "u16" else sc.depth_m, fmt)
+    pad = 5
+    padded = torch.empty((cam.height, cam.width + pad), dtype=dense.dtype, device=dense.device)
+    padded.fill_(900 if fmt == "u16" else 0.9)
+    padded[:, :cam.width].copy_(dense)
+    view = padded[:, :cam.width]
+    assert view.stride(0) == cam.width + pad and view.stride(1) == 1
+    K = (cam.fx, cam.fy, cam.cx, cam.cy)
+    for precision in ("mixed", "fp64"):
+        log(f"[case] pitched rows {fmt} {precision}")
+        p = make_params(radius=5, iterations=5, precision=precision)
+        a = _run_single(ctx, dense, cam, p)
+        b = _run_single(ctx, view, cam, p)
+        assert (a["flags"] & 1).sum() > cam.width * cam.height // 2
+        _equal(a, b, f"pitched {fmt} {precision}")
+    log(f"[case] pitched rows {fmt} in a batch")
+    ref = _run_single(ctx, dense, cam, make_params(radius=5, iterations=5))
+    outs = ctx.fit_batch([(view, K, make_params(radius=5, iterations=5), None),
+                          (dense, K, make_params(radius=3, iterations=3), None)])
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in outs[0].items()}
+    for key in ("k1", "k2", "flags"):
+        assert np.array_equal(got[key], ref[key], equal_nan=True), f"batched pitched {fmt}: {key}"

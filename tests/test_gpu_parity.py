@@ -170,3 +170,60 @@ def test_strided_with_rejection(ctx):
     cam = scenes.Camera(100, 75, 90.0, 90.0, 49.5, 37.0)
     sc = scenes.cluttered_scene(cam, seed_frame=16, config_index=8)
     _run(ctx, "stride+reject", sc.depth_u16(), "u16", cam, 8, 5, 1e-3, stride=2, reject=True)
+
+
+def test_invalid_arguments_rejected_before_any_launch(ctx):
+    """qc_fit checks every argument before it enqueues anything: each malformed frame,
+    parameter set or output set returns QC_ERR_INVALID_ARG and leaves the outputs as they
+    were; the well-formed call then succeeds."""
+    import ctypes
+    import torch
+    from paper_1707_00385_amd import _lib
+    from paper_1707_00385_amd.api import make_frame, make_outputs, make_params, output_struct, upload_depth
+    cam = scenes.Camera(48, 40, 50.0, 50.0, 23.5, 19.5)
+    sc = scenes.cluttered_scene(cam, seed_frame=5, config_index=9)
+    depth = upload_depth(sc.depth_u16(), "u16")
+    out = make_outputs(cam.height, cam.width, depth.device, normal=True, residual=True)
+    for t in out.values():
+        t.fill_(7)
+    torch.cuda.synchronize()
+    before = {k: v.cpu().numpy().copy() for k, v in out.items()}
+    good_f = make_frame(depth, (cam.fx, cam.fy, cam.cx, cam.cy))
+    good_p = make_params(radius=3, iterations=3)
+    good_o = output_struct(out)
+
+    def call(f, p, o):
+        st = torch.cuda.current_stream(depth.device).cuda_stream
+        return ctx._lib.qc_fit(ctx._h, ctypes.byref(f), ctypes.byref(p), ctypes.byref(o),
+                               ctypes.c_void_p(st))
+
+    def variant(struct, **fields):
+        c = type(struct).from_buffer_copy(struct)
+        for name, value in fields.items():
+            if name in ("fx", "fy", "cx", "cy"):
+                setattr(c.K, name, value)
+            else:
+                setattr(c, name, value)
+        return c
+
+    nan, inf = float("nan"), float("inf")
+    frames = [dict(pitch_bytes=cam.width * 2 - 2), dict(pitch_bytes=cam.width * 2 + 1),
+              dict(width=0), dict(height=-1), dict(format=7), dict(depth=None),
+              dict(fx=0.0), dict(fy=-1.0), dict(cx=nan), dict(fx=inf)]
+    params = [dict(radius=0), dict(radius=_lib.QC_MAX_RADIUS + 1), dict(normal_radius=0),
+              dict(iterations=-1), dict(iterations=65), dict(k=0.0), dict(k=nan),
+              dict(depth_scale=0.0), dict(precision=3), dict(tile_width=12), dict(reject=2),
+              dict(stride=0), dict(stride=4), dict(cond_max=nan)]
+    outputs = [dict(k1=None), dict(k2=None)]
+    for fields in frames:
+        assert call(variant(good_f, **fields), good_p, good_o) == _lib.QC_ERR_INVALID_ARG, fields
+    for fields in params:
+        assert call(good_f, variant(good_p, **fields), good_o) == _lib.QC_ERR_INVALID_ARG, fields
+    for fields in outputs:
+        assert call(good_f, good_p, variant(good_o, **fields)) == _lib.QC_ERR_INVALID_ARG, fields
+    torch.cuda.synchronize()
+    for k, v in out.items():
+        assert np.array_equal(v.cpu().numpy(), before[k]), f"{k} written by a rejected call"
+    assert call(good_f, good_p, good_o) == _lib.QC_OK
+    torch.cuda.synchronize()
+    assert ((out["flags"].cpu().numpy() & 1) == 1).sum() > cam.width * cam.height // 2
