@@ -253,3 +253,47 @@ def test_pitched_rows_equal_dense_rows(ctx, fmt):
     got = {k: v.cpu().numpy() for k, v in outs[0].items()}
     for key in ("k1", "k2", "flags"):
         assert np.array_equal(got[key], ref[key], equal_nan=True), f"batched pitched {fmt}: {key}"
+
+
+def test_two_contexts_on_two_host_threads(ctx):
+    """Two contexts, each driven by its own host thread on its own stream, fitting
+    different frames at the same time: every result equals the same fit run alone."""
+    import threading
+    import torch
+    from paper_1707_00385_amd.api import Context, make_params, upload_depth
+    cams = [scenes.Camera(120, 90, 100.0, 100.0, 59.5, 44.5), scenes.Camera(96, 80, 90.0, 90.0, 47.5, 39.5)]
+    work = []
+    for i, cam in enumerate(cams):
+        sc = scenes.cluttered_scene(cam, seed_frame=30 + i, config_index=8)
+        work.append((upload_depth(sc.depth_u16(), "u16"), cam, make_params(radius=4 + i, iterations=5)))
+    alone = [_run_single(ctx, t, cam, p) for t, cam, p in work]
+    log("[case] two contexts on two host threads")
+    results = [[None] * 4 for _ in work]
+    errors = []
+
+    def worker(i):
+        try:
+            t, cam, p = work[i]
+            c = Context(0)
+            s = torch.cuda.Stream(device=t.device)
+            from paper_1707_00385_amd.api import make_outputs
+            for rep in range(4):
+                o = make_outputs(t.shape[0], t.shape[1], t.device, normal=True, residual=True)
+                with torch.cuda.stream(s):
+                    c.fit(t, (cam.fx, cam.fy, cam.cx, cam.cy), params=p, out=o, stream=s)
+                s.synchronize()
+                results[i][rep] = {k: v.cpu().numpy() for k, v in o.items()}
+            c.close()
+        except Exception as e:  # reported on the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(i,)) for i in range(len(work))]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=60)
+    assert not any(th.is_alive() for th in threads), "a worker thread did not finish"
+    assert not errors, errors
+    for i, reps in enumerate(results):
+        for rep, r in enumerate(reps):
+            _equal(r, alone[i], f"thread {i} call {rep}")
