@@ -127,7 +127,10 @@ qc_status qc_destroy(qc_context* ctx);
 
 /* Fits every pixel of one frame (Section 3.2).  Asynchronous on `stream`.  The
  * context's refit scratch is reused by the next call on the same context, so calls on
- * one context must be ordered on one stream. */
+ * one context must be ordered on one stream.  The first call for a larger frame grows
+ * that scratch (an allocation, after waiting for the device); later calls for frames
+ * no larger, with kernel timing off, only enqueue kernels on `stream` and may be
+ * captured in a HIP graph. */
 qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params,
                  const qc_output* out, void* stream);
 

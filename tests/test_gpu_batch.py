@@ -297,3 +297,38 @@ def test_two_contexts_on_two_host_threads(ctx):
     for i, reps in enumerate(results):
         for rep, r in enumerate(reps):
             _equal(r, alone[i], f"thread {i} call {rep}")
+
+
+def test_caller_captured_fit_replays_match_eager(ctx):
+    """Once a context holds the scratch a frame size needs, qc_fit only enqueues kernels
+    (no allocation, no synchronisation, no memset node), so a caller can capture it in a
+    HIP graph.  The graph is replayed over new depth contents, with eager work and
+    synchronisations between replays, and every replay equals the eager fit."""
+    import torch
+    from paper_1707_00385_amd.api import make_outputs, make_params, upload_depth
+    cam = scenes.Camera(128, 96, 110.0, 110.0, 63.5, 47.5)
+    frames = [scenes.cluttered_scene(cam, seed_frame=40 + i, config_index=8).depth_u16() for i in range(4)]
+    p = make_params(radius=5, iterations=5)
+    K = (cam.fx, cam.fy, cam.cx, cam.cy)
+    eager = [_run_single(ctx, upload_depth(f, "u16"), cam, p) for f in frames]
+    depth = upload_depth(frames[0], "u16")
+    out = make_outputs(cam.height, cam.width, depth.device, normal=True, residual=True)
+    ctx.fit(depth, K, params=p, out=out)          # sizes the context's scratch outside the capture
+    torch.cuda.synchronize()
+    log("[case] caller-captured qc_fit, 3 replays per frame")
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            ctx.fit(depth, K, params=p, out=out, stream=side)
+    torch.cuda.synchronize()
+    for i, f in enumerate(frames):
+        for rep in range(3):
+            depth.copy_(upload_depth(f, "u16"))
+            for t in out.values():
+                t.fill_(3)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            _equal({k: v.cpu().numpy() for k, v in out.items()}, eager[i], f"frame {i} replay {rep}")
