@@ -86,7 +86,8 @@ typedef struct {
     float cond_max;          /* MIXED: refit if the equilibrated pivot ratio exceeds this */
     float step_max;          /* MIXED: refit if the last update exceeds this, measured in
                                 window units: radians, t_z / h_w and h_w * (A, B, C), with
-                                h_w = r Z / fx the window half-extent at the pixel */
+                                h_w = r Z / fx the window half-extent at the pixel; for
+                                r > 7 (any stride) the bound applied is step_max * (7/r)^2 */
     int32_t tile_width;      /* FP32 pass tile: 8, 16, 32 or 64 pixels wide (256 pixels);
                                 0 = the width qc_tune recorded for this frame size, radius
                                 and iteration count, else 16.  Results do not depend on it. */

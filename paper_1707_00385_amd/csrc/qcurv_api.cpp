@@ -144,7 +144,12 @@ qc::FitDesc make_desc(const qc_frame* frame, const qc_params* params, const qc_o
     d.iterations = params->iterations;
     d.k = params->k;
     d.cond_max = params->cond_max;
-    d.step_max = params->step_max;
+    // step_max is stated for windows reaching up to 7 pixels from the centre; beyond, an
+    // FP32 fit whose last update is smaller still can be outside the tolerance (measured
+    // for dense windows at r = 10, 13 and 16 and for 25x25 sampled every 2nd pixel), so the
+    // bound tightens as (7 / r)^2, r being the reach whatever the stride.
+    const int r = params->radius;
+    d.step_max = r > 7 ? params->step_max * (49.f / static_cast<float>(r * r)) : params->step_max;
     d.precision = params->precision;
     d.reject = params->reject;
     d.stride = params->stride;
