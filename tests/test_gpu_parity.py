@@ -68,6 +68,14 @@ def test_vga_headline_full_frame(ctx):
     log("  refit fraction", st["refits"] / st["pixels"])
 
 
+def test_vga_headline_frame_at_r10(ctx):
+    """The headline scene's first frame at r = 10 (21x21), every pixel.  With the update
+    bound of 0.1 window units applied unscaled, one pixel of this frame (row 149, column
+    328) was left to FP32 at 2.4 times the tolerance; the bound now tightens as (7/r)^2."""
+    sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=0, config_index=1)
+    _run(ctx, "vga u16 noisy r=10", sc.depth_u16(), "u16", sc.camera, 10, 5, 1e-3)
+
+
 def test_vga_noiseless_full_frame(ctx):
     sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=1, config_index=1, noise=False,
                                 dropout=0.0)
