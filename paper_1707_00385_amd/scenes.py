@@ -436,20 +436,23 @@ def cluttered_scene(camera: Camera = CAM_VGA, seed_frame: int = 0, config_index:
 
 def quadric_vertex_scene(A: float, B: float, C: float, rot: np.ndarray, distance: float,
                          size: int = 41, f: float = 525.0, vertex_px: Tuple[float, float] = None,
-                         half_extent: float = 0.1) -> Tuple[Scene, Tuple[int, int]]:
+                         half_extent: float = 0.1, fy: Optional[float] = None
+                         ) -> Tuple[Scene, Tuple[int, int]]:
     """A parabolic patch whose vertex sits on a pixel ray, ray-cast exactly.
 
     `rot` columns give the patch's local axes; its local z axis must point away from
-    the camera so that the curvature at the vertex is eig([[A, B], [B, C]])."""
+    the camera so that the curvature at the vertex is eig([[A, B], [B, C]]).  The camera
+    has focal lengths f (x) and fy (y; default f)."""
     cx = cy = (size - 1) / 2.0
-    cam = Camera(size, size, f, f, cx, cy)
+    fy = f if fy is None else fy
+    cam = Camera(size, size, f, fy, cx, cy)
     if vertex_px is None:
         vertex_px = (size // 2, size // 2)
     u, v = vertex_px
-    origin = np.array([(u - cx) / f * distance, (v - cy) / f * distance, distance])
+    origin = np.array([(u - cx) / f * distance, (v - cy) / fy * distance, distance])
     shapes = [lambda r: _quadric_patch(r, origin, rot, A, B, C, half_extent)]
     d, k1, k2, n, sid = _composite(cam, shapes)
-    params = dict(kind="quadric_vertex", A=A, B=B, C=C, distance=distance, size=size, f=f)
+    params = dict(kind="quadric_vertex", A=A, B=B, C=C, distance=distance, size=size, f=f, fy=fy)
     sc = Scene(cam, d.copy(), d, k1, k2, n, sid, params)
     return sc, (int(u), int(v))
 

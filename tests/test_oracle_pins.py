@@ -119,6 +119,48 @@ def test_exact_quadric_recovered_at_vertex(radius, distance, f):
         assert o["residual"][0] < 1e-12
 
 
+# Reading R1 (pinhole back-projection) with unequal focal lengths: every other pin uses
+# fx = fy, so these fix that the y coordinate is scaled by fy, not by fx.
+ANISO_FOCAL = [(525.0, 518.9), (131.25, 140.0)]
+
+
+@pytest.mark.parametrize("fx,fy", ANISO_FOCAL)
+def test_exact_quadric_recovered_with_unequal_focal_lengths(fx, fy):
+    """The exact-recovery pin on a camera with fx != fy: the ray-cast patch is exactly a
+    parabolic patch only in the camera's own metric coordinates, so back-projecting y with
+    the wrong focal length distorts it (by (fx/fy)^2 in curvature) and tilts its axis."""
+    rng = np.random.default_rng(700 + int(fy))
+    for trial in range(4):
+        A, B, C = rng.uniform(-20, 20, 3)
+        z = np.array([rng.uniform(-0.4, 0.4), rng.uniform(-0.4, 0.4), 1.0])
+        rot = _frame_with_z(z, rng.uniform(0, 2 * np.pi))
+        sc, (u, v) = scenes.quadric_vertex_scene(A, B, C, rot, distance=0.9, size=23, f=fx, fy=fy)
+        assert sc.camera.fx == fx and sc.camera.fy == fy
+        W = sc.camera.width
+        o = oracle.fit_pixels(sc.depth_m, np.array([v * W + u]), *_cam(sc), radius=7,
+                              iterations=10, k=1e-5)
+        assert o["flags"][0] == 1
+        ev = np.linalg.eigvalsh([[A, B], [B, C]])
+        assert abs(o["k1"][0] - ev[1]) < 1e-8 * max(1, abs(ev[1]))
+        assert abs(o["k2"][0] - ev[0]) < 1e-8 * max(1, abs(ev[0]))
+        np.testing.assert_allclose(o["normal"][0], rot[:, 2], atol=1e-10)
+
+
+@pytest.mark.parametrize("fx,fy", ANISO_FOCAL)
+def test_tilted_plane_with_unequal_focal_lengths(fx, fy):
+    """A tilted plane seen by a camera with fx != fy: flat (k = 0) and with the plane's own
+    normal at every pixel whose window lies inside the image."""
+    cam = scenes.Camera(48, 40, fx, fy, 23.5, 19.5)
+    for nrm in ([0.3, -0.4, 1.0], [-0.5, 0.6, 0.8]):
+        sc = scenes.plane_scene(nrm, 1.1, cam)
+        o = oracle.fit_image(sc.depth_m, *_cam(sc), radius=4, iterations=3, k=1e-5)
+        v = o["flags"] == 1
+        assert v[4:-4, 4:-4].all()
+        assert np.nanmax(np.abs(o["k1"][v])) < 1e-8 and np.nanmax(np.abs(o["k2"][v])) < 1e-8
+        want = np.asarray(nrm) / np.linalg.norm(nrm)
+        assert np.abs(o["normal"][v] - want).max() < 1e-9
+
+
 def _vertex_fit(sc, radius, iterations=10, k=1e-5):
     c = sc.camera
     u, v = int(round(c.cx)), int(round(c.cy))
@@ -277,13 +319,20 @@ def test_one_step_is_weighted_gauss_newton():
         np.testing.assert_allclose(o["normal"], n1, atol=1e-8)
 
 
-def _scipy_fit(pts, ci, n0, loss, k):
+def _scipy_solution(pts, ci, n0, loss, k, keep=None):
+    """SciPy's trust-region solution x = (ax, ay, tz, A, B, C) on the points `keep` (all by
+    default), and the residual vector of every point at x."""
     pc = pts - pts[ci]
     R0 = _min_rotation_to_z(n0)
-    sol = least_squares(_model_residuals, np.zeros(6), args=(pc, R0), loss=loss,
+    sel = pc if keep is None else pc[keep]
+    sol = least_squares(_model_residuals, np.zeros(6), args=(sel, R0), loss=loss,
                         f_scale=math.sqrt(k), xtol=1e-15, ftol=1e-15, gtol=1e-15,
                         max_nfev=20000, method="trf")
-    x = sol.x
+    return sol.x, _model_residuals(sol.x, pc, R0), R0
+
+
+def _scipy_fit(pts, ci, n0, loss, k):
+    x, _, R0 = _scipy_solution(pts, ci, n0, loss, k)
     ev = np.linalg.eigvalsh([[x[3], x[4]], [x[4], x[5]]])
     n = (Rotation.from_rotvec([x[0], x[1], 0]).as_matrix() @ R0)[2]
     return ev[1], ev[0], n
@@ -305,6 +354,26 @@ def test_converged_irls_is_the_cauchy_m_estimator(loss, k):
         assert abs(o["k1"] - k1s) < 1e-6 * max(1, abs(k1s))
         assert abs(o["k2"] - k2s) < 1e-6 * max(1, abs(k2s))
         np.testing.assert_allclose(o["normal"], ns, atol=1e-9)
+
+
+def test_residual_is_the_weighted_rms_at_the_converged_fit():
+    """Reading R11: the residual output is sqrt(sum w e^2 / sum w) with the weights of
+    Eq. (11) at the final parameters.  Its expected value is computed from SciPy's
+    converged Cauchy solution (residual vector of the model at SciPy's x), on noisy patches
+    where e^2 is comparable to k, so that this weighted RMS and the plain RMS of the
+    residuals differ by far more than the tolerance."""
+    sc = scenes.sphere_on_plane(noise=True)
+    k = 4e-7
+    for (u, v) in [(80, 60), (76, 55), (86, 63)]:
+        pts, ci = _patch_points(sc, u, v, 5)
+        n0 = _lstsq_normal(_patch_points(sc, u, v, 3)[0])
+        _, e, _ = _scipy_solution(pts, ci, n0, "cauchy", k)
+        w = k / (k + e ** 2)
+        want = math.sqrt(np.sum(w * e ** 2) / np.sum(w))
+        plain = math.sqrt(np.mean(e ** 2))
+        assert abs(plain - want) > 0.02 * want        # the pin tells the two apart
+        o = oracle.fit_patch(pts, ci, n0, iterations=300, k=k)
+        assert abs(o["residual"] - want) < 1e-6 * want
 
 
 # --------------------------------------------------------------------------- invariances
@@ -409,6 +478,52 @@ def test_rejection_filter_removes_gross_outlier():
     keep = oracle.fit_patch(bad, ci, n0, iterations=8, k=1e-6, reject=False)
     assert abs(rej["k1"] - ev[1]) < 1e-8 and abs(rej["k2"] - ev[0]) < 1e-8
     assert abs(keep["k1"] - ev[1]) + abs(keep["k2"] - ev[0]) > 1e-6
+
+
+def test_rejection_threshold_is_twice_the_mse():
+    """Eq. (11) with R = 2 MSE (Section 3.2.3): at the converged fit a point is kept when
+    e^2 < 2 MSE, MSE the unweighted mean of e^2 over the window (reading R7).  A tilted
+    plane carries a checkerboard of +-1 mm depth offsets (which a parabolic patch cannot
+    follow, so every such point keeps |e| close to 1 mm) plus two larger offsets: point a
+    ends with e^2 between MSE and 2 MSE (kept; a bound of 1 MSE would drop it) and point b
+    with e^2 between 2 MSE and 4 MSE (dropped; a bound of 4 MSE would keep it).  The
+    expected curvatures, normal and residual come from SciPy's Cauchy fit of all points but
+    b, with k = 100 sigma^2 so that the robust loss is convex over these residuals."""
+    f, r, sigma, k = 525.0, 7, 1e-3, 1e-4
+    du, dv = np.meshgrid(np.arange(-r, r + 1), np.arange(-r, r + 1))
+    x_r, y_r = du.ravel() / f, dv.ravel() / f           # pixel rays
+    Z = 1.0 / (1.0 - 0.2 * x_r + 0.1 * y_r)             # the plane Z = 1 + 0.2 X - 0.1 Y
+    offset = sigma * ((-1.0) ** (du + dv)).ravel()
+    ci = Z.size // 2
+    ia, ib = 40, 150
+    offset[ci] = 0.0
+    offset[ia] *= 1.2
+    offset[ib] *= 1.7
+    Zp = Z + offset
+    pts = np.stack([x_r * Zp, y_r * Zp, Zp], 1)
+    n0 = np.array([-0.2, 0.1, 1.0]) / math.sqrt(1.05)
+    keep = np.ones(Z.size, dtype=bool)
+    keep[ib] = False
+    x, e, R0 = _scipy_solution(pts, ci, n0, "cauchy", k, keep=keep)
+    mse = np.mean(e ** 2)
+    # the premise: at the kept points' solution, b is the only point at or beyond 2 MSE,
+    # a lies between MSE and 2 MSE, and b below 4 MSE
+    assert mse < e[ia] ** 2 < 2 * mse < e[ib] ** 2 < 4 * mse
+    assert np.all(np.delete(e, ib) ** 2 < 2 * mse)
+    ev = np.linalg.eigvalsh([[x[3], x[4]], [x[4], x[5]]])
+    n = (Rotation.from_rotvec([x[0], x[1], 0]).as_matrix() @ R0)[2]
+    w = np.where(keep, k / (k + e ** 2), 0.0)
+    res = math.sqrt(np.sum(w * e ** 2) / np.sum(w))
+    o = oracle.fit_patch(pts, ci, n0, iterations=200, k=k, reject=True)
+    assert o["valid"]
+    assert abs(o["k1"] - ev[1]) < 2e-6 and abs(o["k2"] - ev[0]) < 2e-6
+    np.testing.assert_allclose(o["normal"], n, atol=1e-9)
+    assert abs(o["residual"] - res) < 1e-6 * res
+    # dropping a as well, or keeping b, moves the fit far beyond that tolerance
+    for alt in (keep & (np.arange(Z.size) != ia), np.ones(Z.size, dtype=bool)):
+        xa, _, _ = _scipy_solution(pts, ci, n0, "cauchy", k, keep=alt)
+        eva = np.linalg.eigvalsh([[xa[3], xa[4]], [xa[4], xa[5]]])
+        assert max(abs(eva[1] - ev[1]), abs(eva[0] - ev[0])) > 1e-2
 
 
 # ---- strided ("sparsely sampled") patch: the large patch of the timings of Section 4 ----
