@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_1707_00385_amd import scenes
-from tests.helpers import compare, gpu_fit, log, oracle_pair
+from tests.helpers import compare, gpu_fit, log, oracle_pair, window_crosses_edge
 
 pytestmark = pytest.mark.gpu
 
@@ -26,14 +26,15 @@ def ctx():
 
 
 def _run(ctx, name, depth, fmt, cam, radius, iterations, tol, precision="mixed", k=1e-5,
-         normal_radius=3, reject=False, stride=1, **kw):
-    log(f"[case] {name} fmt={fmt} {cam.width}x{cam.height} r={radius} T={iterations} {precision}"
-        f"{' reject' if reject else ''}{f' stride={stride}' if stride > 1 else ''}")
+         normal_radius=3, reject=False, stride=1, scene=None, **kw):
+    log(f"[case] {name} fmt={fmt} {cam.width}x{cam.height} fx={cam.fx} fy={cam.fy} r={radius} "
+        f"T={iterations} {precision}{' reject' if reject else ''}{f' stride={stride}' if stride > 1 else ''}")
     g = gpu_fit(ctx, depth, fmt, cam, radius=radius, iterations=iterations, k=k,
                 normal_radius=normal_radius, precision=precision, reject=int(reject), stride=stride)
     o, oa = oracle_pair(depth, fmt, cam, radius, iterations, k, normal_radius=normal_radius,
                         reject=reject, stride=stride)
-    return compare(g, o, tol, name, o_alt=oa, **kw), g, o
+    edge = window_crosses_edge(scene.surface_id, radius) if scene is not None else None
+    return compare(g, o, tol, name, o_alt=oa, edge=edge, **kw), g, o
 
 
 def test_sphere_on_plane_160x120(ctx):
@@ -64,7 +65,8 @@ def test_clutter_small_formats(ctx, fmt):
 def test_vga_headline_full_frame(ctx):
     """The headline frame: 640x480 Kinect-like u16, r = 7, T = 5, every pixel."""
     sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=0, config_index=1)
-    st, g, o = _run(ctx, "vga u16 noisy", sc.depth_u16(), "u16", sc.camera, 7, 5, 1e-3)
+    st, g, o = _run(ctx, "vga u16 noisy", sc.depth_u16(), "u16", sc.camera, 7, 5, 1e-3, scene=sc,
+                    normal_tol=1e-3, residual_tol=1e-3)
     log("  refit fraction", st["refits"] / st["pixels"])
 
 
@@ -73,13 +75,33 @@ def test_vga_headline_frame_at_r10(ctx):
     bound of 0.1 window units applied unscaled, one pixel of this frame (row 149, column
     328) was left to FP32 at 2.4 times the tolerance; the bound now tightens as (7/r)^2."""
     sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=0, config_index=1)
-    _run(ctx, "vga u16 noisy r=10", sc.depth_u16(), "u16", sc.camera, 10, 5, 1e-3)
+    _run(ctx, "vga u16 noisy r=10", sc.depth_u16(), "u16", sc.camera, 10, 5, 1e-3, scene=sc)
 
 
 def test_vga_noiseless_full_frame(ctx):
     sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=1, config_index=1, noise=False,
                                 dropout=0.0)
-    _run(ctx, "vga f32 noiseless", sc.depth_m, "f32", sc.camera, 7, 5, 1e-4)
+    _run(ctx, "vga f32 noiseless", sc.depth_m, "f32", sc.camera, 7, 5, 1e-4, scene=sc,
+         normal_tol=1e-4, residual_tol=1e-3)
+
+
+# A camera whose focal lengths differ (pixels 1.2 % taller than wide): back-projection
+# divides the row offset by fy and the column offset by fx (Section 3.2, pinhole model).
+CAM_VGA_ANISO = scenes.Camera(640, 480, 525.0, 518.9, 319.5, 239.5)
+
+
+@pytest.mark.parametrize("noise", [False, True])
+def test_vga_unequal_focal_lengths_full_frame(ctx, noise):
+    """Every pixel of a 640x480 frame with fx != fy: noisy u16 at 1e-3, noiseless f32 at
+    1e-4 (a kernel that used fx for the rows would be off by about 1 % in curvature)."""
+    sc = scenes.cluttered_scene(CAM_VGA_ANISO, seed_frame=4, config_index=1, noise=noise,
+                                dropout=0.02 if noise else 0.0)
+    if noise:
+        _run(ctx, "vga fx!=fy u16 noisy", sc.depth_u16(), "u16", sc.camera, 7, 5, 1e-3, scene=sc,
+             normal_tol=1e-3, residual_tol=1e-3)
+    else:
+        _run(ctx, "vga fx!=fy f32 noiseless", sc.depth_m, "f32", sc.camera, 7, 5, 1e-4, scene=sc,
+             normal_tol=1e-4, residual_tol=1e-3)
 
 
 @pytest.mark.parametrize("w,h,r", [(1, 1, 1), (5, 3, 2), (17, 16, 3), (33, 31, 18)])
@@ -156,14 +178,25 @@ def test_strided_window_small(ctx, radius, stride, nonunique):
     cam = scenes.Camera(100, 75, 90.0, 90.0, 49.5, 37.0)
     sc = scenes.cluttered_scene(cam, seed_frame=14, config_index=8)
     _run(ctx, f"stride clutter100x75 r={radius} s={stride}", sc.depth_u16(), "u16", cam, radius, 5,
-         1e-3, stride=stride, residual_tol=1e-2, max_nonunique=nonunique)
+         1e-3, stride=stride, residual_tol=1e-2, max_nonunique=nonunique, scene=sc)
 
 
 def test_strided_paper_patch_vga(ctx):
     """The paper's largest patch, 37x37, sampled every third pixel (13x13 samples), on a
     full headline-like frame."""
     sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=3, config_index=1)
-    st, g, _ = _run(ctx, "stride vga 37x37/3", sc.depth_u16(), "u16", sc.camera, 18, 5, 1e-3, stride=3)
+    st, g, _ = _run(ctx, "stride vga 37x37/3", sc.depth_u16(), "u16", sc.camera, 18, 5, 1e-3, stride=3,
+                    scene=sc)
+    log("  refit fraction", st["refits"] / st["pixels"])
+
+
+def test_strided_paper_patch_vga_noiseless(ctx):
+    """The 37x37 patch sampled every third pixel on a noiseless 640x480 frame, every pixel,
+    at the noiseless tolerance 1e-4."""
+    sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=1, config_index=1, noise=False,
+                                dropout=0.0)
+    st, g, _ = _run(ctx, "stride vga 37x37/3 noiseless", sc.depth_m, "f32", sc.camera, 18, 5, 1e-4,
+                    stride=3, scene=sc)
     log("  refit fraction", st["refits"] / st["pixels"])
 
 

@@ -76,3 +76,32 @@ def test_traffic_record_key_ignores_comments_only():
     assert bench._code_only(src) == bench._code_only(same)
     assert bench._code_only(src) != bench._code_only(other)
     assert '"// kept"' in bench._code_only(src)
+
+
+def test_parity_harness_holds_non_unique_pixels_to_the_oracle_envelope():
+    """The GPU parity harness (tests/helpers.compare) on CPU data: a perturbed oracle run
+    passes as the 'GPU' result, every non-unique pixel of this noiseless clutter frame
+    lies on a depth edge, and a planted error at one non-unique pixel (k1 moved by 20 %,
+    outside the envelope of seven oracle runs) fails the comparison even though such
+    pixels are not compared with the oracle itself."""
+    import sys
+    import numpy as np
+    import pytest
+    sys.path.insert(0, ROOT)
+    from paper_1707_00385_amd import scenes
+    from tests.helpers import compare, oracle_pair, window_crosses_edge
+    cam = scenes.Camera(160, 120, 140.0, 140.0, 79.5, 59.5)
+    sc = scenes.cluttered_scene(cam, seed_frame=3, config_index=8, noise=False, dropout=0.0)
+    d = sc.depth_m.astype(np.float32)
+    o, probe = oracle_pair(d, "f32", cam, 7, 5, 1e-5)
+    g = {k: (v.astype(np.float32) if k != "flags" else v.copy()) for k, v in probe.runs[0].items()}
+    edge = window_crosses_edge(sc.surface_id, 7)
+    st = compare(g, o, 1e-4, "perturbed run as GPU", o_alt=probe, edge=edge)
+    assert st["nonunique"] > 0 and st["nonunique_at_edges"] == st["nonunique"]
+    assert st["nonunique_outside_envelope"] == 0
+    sens = np.maximum(np.abs(probe["k1"] - o["k1"]), np.abs(probe["k2"] - o["k2"]))
+    ij = np.unravel_index(np.nanargmax(np.where(o["flags"] == 1, sens, -1)), sens.shape)
+    g["k1"][ij] = np.float32(o["k1"][ij] + 0.2 * max(abs(o["k1"][ij]), 1.0))
+    g["k2"][ij] = min(g["k2"][ij], g["k1"][ij])
+    with pytest.raises(AssertionError, match="outside the oracle's envelope"):
+        compare(g, o, 1e-4, "planted error", o_alt=probe, edge=edge)
