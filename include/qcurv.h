@@ -129,9 +129,9 @@ qc_status qc_destroy(qc_context* ctx);
 /* Fits every pixel of one frame (Section 3.2).  Asynchronous on `stream`.  The
  * context's refit scratch is reused by the next call on the same context, so calls on
  * one context must be ordered on one stream.  The first call for a larger frame grows
- * that scratch (an allocation, after waiting for the device); later calls for frames
- * no larger, with kernel timing off, only enqueue kernels on `stream` and may be
- * captured in a HIP graph. */
+ * that scratch: it waits for the stream of the context's previous fit (which must still
+ * exist) and allocates; later calls for frames no larger, with kernel timing off, only
+ * enqueue kernels on `stream` and may be captured in a HIP graph. */
 qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params,
                  const qc_output* out, void* stream);
 
@@ -213,7 +213,9 @@ typedef struct {
     const uint8_t* flags;
 } qc_completion;
 
-/* Starts a server on `ctx` (its device) with the given configuration. */
+/* Starts a server on `ctx` (its device) with the given configuration.  A batch holds
+ * frames of one precision: the oldest ready frame's, with the ready frames of the other
+ * precision left, in order, for the next batch. */
 qc_status qc_server_create(qc_context* ctx, const qc_server_config* config, qc_server** out);
 
 /* Queues one frame; *ticket identifies it.  Returns QC_ERR_BUSY when the pinned staging
@@ -237,7 +239,9 @@ typedef struct {
 } qc_server_stats;
 qc_status qc_server_get_stats(qc_server* server, qc_server_stats* out);
 
-/* Waits for all submitted frames, stops the server and frees its memory. */
+/* Waits for all submitted frames, stops the server and frees its memory.  Frames that
+ * still wait for device memory held by unreleased results, once nothing else is on the GPU,
+ * are not fitted: they complete with QC_ERR_BUSY (no release can come during destruction). */
 qc_status qc_server_destroy(qc_server* server);
 
 /* Number of pixels recomputed in FP64 by the most recent qc_fit on this context
@@ -248,7 +252,9 @@ qc_status qc_last_refit_count(qc_context* ctx, uint32_t* count);
  * around its kernels on the call's stream: the FP32 (or FP64-only) fitting pass and the
  * FP64 recomputation pass.  qc_get_timing waits for the recorded events, returns the
  * sums since the last reset (milliseconds) and, if `reset` is non-zero, clears them.
- * Timing adds two or three event records per call and is off by default. */
+ * The events come from a pool of 1024 triples that the first qc_set_timing(ctx, 1)
+ * creates; a timed call only records three of them, except that once all are recorded
+ * and unread the call first waits for the oldest.  Off by default. */
 typedef struct {
     uint64_t calls;       /* qc_fit calls timed */
     double fit_ms;        /* summed duration of the tiled fitting pass */

@@ -15,6 +15,7 @@ LIB_PATH = os.environ.get("QCURV_LIB") or os.path.join(PKG, "libqcurv.so")
 
 QC_OK = 0
 QC_ERR_INVALID_ARG = -1
+QC_ERR_UNSUPPORTED = -2
 QC_DEPTH_U16, QC_DEPTH_F16, QC_DEPTH_F32 = 0, 1, 2
 QC_PREC_MIXED, QC_PREC_FP32, QC_PREC_FP64 = 0, 1, 2
 QC_FLAG_VALID, QC_FLAG_FP64, QC_FLAG_ILLCOND = 1, 2, 4

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <new>
 #include <tuple>
@@ -54,9 +55,11 @@ struct qc_context {
     int64_t capacity = 0;
     hipStream_t last_stream = nullptr;
     int last_precision = 0;
-    // timing: recorded event triples not yet read, and the sums of those already read
+    // timing: a pool of event triples created once (qc_set_timing), the triples recorded
+    // and not yet read (oldest first), the free ones, and the sums of those already read
     bool timing = false;
-    std::vector<hipEvent_t> pending;
+    std::vector<hipEvent_t> events;     // 3 per triple
+    std::deque<int> pending, free_triples;
     qc_timing sums{};
     // batches
     BatchSlot slots[2];
@@ -71,6 +74,42 @@ namespace {
 qc_status hip_fail(qc_context* ctx, hipError_t e) {
     if (ctx) ctx->last_hip_error = static_cast<int>(e);
     return e == hipErrorOutOfMemory ? QC_ERR_OOM : QC_ERR_HIP;
+}
+
+// Triples of timing events per context: enough for every call of a long timed loop to
+// record without waiting; beyond that the oldest triple is read (waiting for it) and reused.
+constexpr int kTimingTriples = 1024;
+
+// Folds the oldest recorded triple into the sums (waits for its last event) and frees it.
+qc_status fold_oldest(qc_context* ctx) {
+    const int t = ctx->pending.front();
+    ctx->pending.pop_front();
+    ctx->free_triples.push_back(t);
+    hipEvent_t* ev = &ctx->events[3 * static_cast<size_t>(t)];
+    float a = 0.f, b = 0.f;
+    hipError_t e;
+    if ((e = hipEventSynchronize(ev[2])) != hipSuccess || (e = hipEventElapsedTime(&a, ev[0], ev[1])) != hipSuccess ||
+        (e = hipEventElapsedTime(&b, ev[1], ev[2])) != hipSuccess)
+        return hip_fail(ctx, e);
+    ctx->sums.calls += 1;
+    ctx->sums.fit_ms += a;
+    ctx->sums.refit_ms += b;
+    return QC_OK;
+}
+
+// The events of a free triple for the next timed call (nullptr when timing is off).
+qc_status next_triple(qc_context* ctx, hipEvent_t** ev) {
+    *ev = nullptr;
+    if (!ctx->timing) return QC_OK;
+    if (ctx->free_triples.empty()) {
+        const qc_status st = fold_oldest(ctx);
+        if (st != QC_OK) return st;
+    }
+    const int t = ctx->free_triples.front();
+    ctx->free_triples.pop_front();
+    ctx->pending.push_back(t);
+    *ev = &ctx->events[3 * static_cast<size_t>(t)];
+    return QC_OK;
 }
 
 int sample_bytes(int32_t format) {
@@ -166,8 +205,10 @@ qc_status ensure_capacity(qc_context* ctx, int64_t entries) {
     if (ctx->capacity >= entries) return QC_OK;
     hipError_t e;
     if (ctx->refit_storage) {
-        // the previous list may still be in use by enqueued work
-        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(ctx, e);
+        // the previous list may still be in use by the previous call's work, which is on
+        // that call's stream (calls on one context are ordered on one stream): wait for
+        // that stream only, not for other contexts' or streams' work
+        if ((e = hipStreamSynchronize(ctx->last_stream)) != hipSuccess) return hip_fail(ctx, e);
         (void)hipFree(ctx->refit_storage);
         ctx->refit_storage = nullptr;
         ctx->capacity = 0;
@@ -301,7 +342,7 @@ qc_status qc_destroy(qc_context* ctx) {
     (void)hipDeviceSynchronize();
     if (ctx->refit_storage) (void)hipFree(ctx->refit_storage);
     if (ctx->refit_counts) (void)hipFree(ctx->refit_counts);
-    for (hipEvent_t ev : ctx->pending) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
     for (BatchSlot& s : ctx->slots) {
         free_slot(s);
         if (s.host) (void)hipHostFree(s.host);
@@ -328,15 +369,10 @@ qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params
         return st;
     const qc::FitDesc d = make_desc(frame, params, out, tile_width_for(ctx, frame, params));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    if (ctx->timing) {
-        for (auto& x : ev)
-            if ((e = hipEventCreate(&x)) != hipSuccess) return hip_fail(ctx, e);
-        ctx->pending.insert(ctx->pending.end(), ev, ev + 3);
-    }
+    hipEvent_t* ev = nullptr;
+    if ((st = next_triple(ctx, &ev)) != QC_OK) return st;
     const qc::RefitList list = qc::refit_list(ctx->refit_storage, ctx->capacity, ctx->refit_counts);
-    if ((e = qc::launch_fit(d, list, ctx->cus, s, ctx->timing ? ev : nullptr)) != hipSuccess)
-        return hip_fail(ctx, e);
+    if ((e = qc::launch_fit(d, list, ctx->cus, s, ev)) != hipSuccess) return hip_fail(ctx, e);
     ctx->last_stream = s;
     ctx->last_precision = params->precision;
     return QC_OK;
@@ -401,10 +437,8 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
             if ((e = qc::launch_fit(descs[j], list, ctx->cus, hs)) != hipSuccess) return hip_fail(ctx, e);
     } else if (ctx->timing) {
         // timed batches run eagerly so that the two passes can be bracketed separately
-        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-        for (auto& x : ev)
-            if ((e = hipEventCreate(&x)) != hipSuccess) return hip_fail(ctx, e);
-        ctx->pending.insert(ctx->pending.end(), ev, ev + 3);
+        hipEvent_t* ev = nullptr;
+        if ((st = next_triple(ctx, &ev)) != QC_OK) return st;
         if ((e = hipMemcpyAsync(s.dev, s.host, sizeof(BatchStaging), hipMemcpyHostToDevice, hs)) != hipSuccess ||
             (e = qc::launch_fit_batch(s.dev->frames, s.dev->first_tile, s.dev->header, ctx->cus,
                                       s.refit_lds, qc::refit_list(s.list, s.capacity, s.counts), hs,
@@ -509,6 +543,19 @@ qc_status qc_last_refit_count(qc_context* ctx, uint32_t* count) {
 
 qc_status qc_set_timing(qc_context* ctx, int enable) {
     if (!ctx) return QC_ERR_INVALID_ARG;
+    if (enable && ctx->events.empty()) {
+        hipError_t e;
+        if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
+        std::vector<hipEvent_t> evs(3 * static_cast<size_t>(kTimingTriples), nullptr);
+        for (hipEvent_t& x : evs)
+            if ((e = hipEventCreate(&x)) != hipSuccess) {
+                for (hipEvent_t y : evs)
+                    if (y) (void)hipEventDestroy(y);
+                return hip_fail(ctx, e);
+            }
+        ctx->events = std::move(evs);
+        for (int t = 0; t < kTimingTriples; ++t) ctx->free_triples.push_back(t);
+    }
     ctx->timing = enable != 0;
     return QC_OK;
 }
@@ -518,21 +565,10 @@ qc_status qc_get_timing(qc_context* ctx, qc_timing* out, int reset) {
     hipError_t e;
     if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
     qc_status st = QC_OK;
-    for (size_t i = 0; i + 2 < ctx->pending.size(); i += 3) {
-        hipEvent_t* ev = &ctx->pending[i];
-        float a = 0.f, b = 0.f;
-        if ((e = hipEventSynchronize(ev[2])) != hipSuccess ||
-            (e = hipEventElapsedTime(&a, ev[0], ev[1])) != hipSuccess ||
-            (e = hipEventElapsedTime(&b, ev[1], ev[2])) != hipSuccess) {
-            st = hip_fail(ctx, e);
-        } else {
-            ctx->sums.calls += 1;
-            ctx->sums.fit_ms += a;
-            ctx->sums.refit_ms += b;
-        }
-        for (int j = 0; j < 3; ++j) (void)hipEventDestroy(ev[j]);
+    while (!ctx->pending.empty()) {
+        const qc_status s1 = fold_oldest(ctx);
+        if (s1 != QC_OK) st = s1;
     }
-    ctx->pending.clear();
     *out = ctx->sums;
     if (reset) ctx->sums = qc_timing{};
     return st;

@@ -187,10 +187,17 @@ struct qc_server {
         }
         // launch the next batch
         if (!ready.empty() && static_cast<int>(running.size()) < cfg.max_in_flight) {
+            // a batch holds one precision (qc_fit_batch requires it): the ready frames that
+            // share the oldest one's, in order; the others wait for a later batch
             Batch b;
-            while (!ready.empty() && static_cast<int>(b.reqs.size()) < cfg.max_batch) {
-                b.reqs.push_back(ready.front());
-                ready.pop_front();
+            const int32_t prec = ready.front()->req.params.precision;
+            for (auto it = ready.begin(); it != ready.end() && static_cast<int>(b.reqs.size()) < cfg.max_batch;) {
+                if ((*it)->req.params.precision == prec) {
+                    b.reqs.push_back(*it);
+                    it = ready.erase(it);
+                } else {
+                    ++it;
+                }
             }
             std::vector<qc_batch_item> items(b.reqs.size());
             for (size_t i = 0; i < b.reqs.size(); ++i) {
@@ -250,6 +257,19 @@ struct qc_server {
             const bool busy = !uploading.empty() || !running.empty();
             if (stop && submitted.empty() && !busy && ready.empty()) break;
             if (moved) continue;
+            if (stop && !busy && ready.empty()) {
+                // Stopping, nothing on the GPU, and the frames left wait for device memory
+                // that only a release of completed results could free: no release comes
+                // during destruction, so they complete with QC_ERR_BUSY instead.
+                while (!submitted.empty()) {
+                    Request* q = submitted.front();
+                    submitted.pop_front();
+                    pin_alloc.release(q->stage_off, q->frame_bytes);
+                    complete(q, QC_ERR_BUSY);
+                }
+                done_cv.notify_all();
+                continue;
+            }
             // Nothing moved.  With GPU work outstanding, poll its events; otherwise every
             // change that could let work move (a submission, a release of memory, stop)
             // notifies work_cv under mu, so a plain wait cannot miss it.  (Waiting on a

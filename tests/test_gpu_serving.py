@@ -1,6 +1,7 @@
 """GPU tests of the serving loop: frames of mixed sizes and window radii submitted from
 host memory are admitted by device memory, batched as they arrive and fitted; each result
 must equal, bit for bit, the plain per-frame fit of the same frame alone."""
+import threading
 import time
 
 import numpy as np
@@ -27,12 +28,13 @@ def frames():
     return out
 
 
-def _alone(ctx, depth, cam, r, T):
+def _alone(ctx, depth, cam, r, T, precision="mixed"):
     import torch
     from paper_1707_00385_amd.api import make_outputs, make_params, upload_depth
     t = upload_depth(depth, "u16")
     o = make_outputs(t.shape[0], t.shape[1], t.device, normal=True, residual=True)
-    ctx.fit(t, (cam.fx, cam.fy, cam.cx, cam.cy), params=make_params(radius=r, iterations=T), out=o)
+    ctx.fit(t, (cam.fx, cam.fy, cam.cx, cam.cy), params=make_params(radius=r, iterations=T, precision=precision),
+            out=o)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in o.items()}
 
@@ -136,3 +138,63 @@ def test_rejects_frames_that_can_never_fit(frames):
     finally:
         srv.close()
         ctx.close()
+
+
+def test_mixed_and_fp32_requests_share_the_server(frames):
+    """MIXED and FP32 requests interleaved in one server: a batch holds frames of one
+    precision, so every request completes with status 0, and each result equals the same
+    frame fitted alone at its own precision, bit for bit."""
+    from paper_1707_00385_amd import _lib
+    from paper_1707_00385_amd.api import Context, Server, make_params
+    ctx_alone = Context(0)
+    precs = ("mixed", "fp32")
+    ref = {(i, p): _alone(ctx_alone, d, cam, r, T, precision=p)
+           for i, (d, cam, r, T) in enumerate(frames) for p in precs}
+    ctx = Context(0)
+    srv = Server(ctx, memory_budget=64 << 20, max_batch=8, max_in_flight=2,
+                 outputs=_lib.QC_OUT_NORMAL | _lib.QC_OUT_RESIDUAL | _lib.QC_OUT_FLAGS)
+    try:
+        jobs = [(i, precs[j % 2]) for j, i in enumerate([0, 1, 2, 3, 1, 0, 3, 2, 2, 3, 0, 1])]
+        for j, (i, p) in enumerate(jobs):
+            d, cam, r, T = frames[i]
+            t = srv.submit(d, "u16", (cam.fx, cam.fy, cam.cx, cam.cy),
+                           make_params(radius=r, iterations=T, precision=p), tag=j)
+            assert t is not None
+        done = _drain(srv, len(jobs))
+        log("[case] served mixed precisions", len(done), "frames; stats", srv.stats())
+        for c in done:
+            assert c.status == 0, (c.tag, c.status)
+            got = _served(c, None)
+            for key, val in ref[jobs[c.tag]].items():
+                assert np.array_equal(got[key], val, equal_nan=True), (jobs[c.tag], key)
+            srv.release(c.ticket)
+    finally:
+        srv.close()
+        ctx.close()
+        ctx_alone.close()
+
+
+def test_destroy_returns_with_frames_waiting_for_memory(frames):
+    """A budget that holds one frame; three frames submitted and the first completion not
+    released: the other two wait for memory that only a release could free.  Destroying
+    the server returns (those frames complete as busy) instead of waiting for ever."""
+    from paper_1707_00385_amd.api import Context, Server, make_params
+    d, cam, r, T = frames[2]   # 160x120
+    one = d.size * 2 + 2 * d.size * 4 + 3 * 256
+    ctx = Context(0)
+    srv = Server(ctx, memory_budget=one + 4096, max_batch=8)
+    try:
+        for _ in range(3):
+            assert srv.submit(d, "u16", (cam.fx, cam.fy, cam.cx, cam.cy), make_params(radius=r, iterations=T))
+        first = _drain(srv, 1)
+        assert first[0].status == 0
+        time.sleep(0.05)
+        assert srv.stats()["queued"] == 2
+        log("[case] destroy with two frames waiting for memory")
+        th = threading.Thread(target=srv.close, daemon=True)
+        th.start()
+        th.join(30.0)
+        assert not th.is_alive(), "qc_server_destroy did not return"
+    finally:
+        if not srv._h.value:
+            ctx.close()
