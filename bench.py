@@ -157,7 +157,8 @@ def cpu_baseline(frame: np.ndarray, cam, budget_s: float = 10.0, served_samples=
 
 def served_oracle_check(samples, tol: float = 1e-3) -> dict:
     """The oracle at the sampled pixels of served frames (run by the CPU-baseline leg):
-    relative error of k1/k2 (floor 1 m^-1) against the oracle on the same u16 input, over
+    error of k1/k2 relative to the curvature scale max(|k1|, |k2|, 1 m^-1) against the
+    oracle on the same u16 input, over
     pixels the oracle itself gives to within tol/100 under a rounding-level perturbation
     of the depth (the parity tests' rule for pixels determined by their input)."""
     import oracle
@@ -173,13 +174,15 @@ def served_oracle_check(samples, tol: float = 1e-3) -> dict:
         p = oracle.fit_pixels(dp, smp["pixels"], *K, **kw)
         ov, pv = o["flags"] == 1, p["flags"] == 1
         gv = np.isfinite(smp["k1"])
-        def scale_o(a, b):
-            return np.abs(a - b) / np.maximum(np.abs(b), 1.0)
-        sens = np.maximum(scale_o(p["k1"], o["k1"]), scale_o(p["k2"], o["k2"]))
+        def curv_err(a1, a2):
+            # relative to the curvature scale max(|k1|, |k2|, 1 m^-1) of the oracle's result
+            scale = np.maximum(np.maximum(np.abs(o["k1"]), np.abs(o["k2"])), 1.0)
+            return np.maximum(np.abs(a1 - o["k1"]), np.abs(a2 - o["k2"])) / scale
+        sens = curv_err(p["k1"], p["k2"])
         unique = ov & pv & (sens <= tol / 100)
         n_nonunique += int(np.sum(ov & ~unique))
         n_valid_mismatch += int(np.sum((gv != ov) & (ov == pv)))
-        e = np.maximum(scale_o(smp["k1"].astype(np.float64), o["k1"]), scale_o(smp["k2"].astype(np.float64), o["k2"]))
+        e = curv_err(smp["k1"].astype(np.float64), smp["k2"].astype(np.float64))
         errs.append(e[unique & gv])
         frames += 1
     e = np.concatenate(errs) if errs else np.zeros(0)

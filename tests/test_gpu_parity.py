@@ -1,7 +1,7 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 oracle on the same
 seeded inputs, element by element.
 
-Tolerance (relative, against max(|k|, 1 m^-1)): 1e-4 on noiseless input, 1e-3 on noisy
+Tolerance (relative to the curvature scale max(|k1|, |k2|, 1 m^-1)): 1e-4 on noiseless input, 1e-3 on noisy
 input, in k1 and k2 of every pixel whose oracle result is unique at that tolerance (see
 tests/helpers.compare).  FP64 mode must agree to 2e-7: its outputs are stored as FP32,
 whose rounding alone is up to 2^-24 relative.

@@ -82,7 +82,7 @@ def test_parity_harness_holds_non_unique_pixels_to_the_oracle_envelope():
     """The GPU parity harness (tests/helpers.compare) on CPU data: a perturbed oracle run
     passes as the 'GPU' result, every non-unique pixel of this noiseless clutter frame
     lies on a depth edge, and a planted error at one non-unique pixel (k1 moved by 20 %,
-    outside the envelope of seven oracle runs) fails the comparison even though such
+    outside the envelope of sixteen oracle runs) fails the comparison even though such
     pixels are not compared with the oracle itself."""
     import sys
     import numpy as np
