@@ -42,7 +42,8 @@ typedef enum {
     QC_ERR_OOM = -3,           /* device scratch could not be allocated */
     QC_ERR_HIP = -4,           /* a HIP runtime call failed (see qc_last_hip_error) */
     QC_ERR_BUSY = -5,          /* the request cannot be admitted now; retry later */
-    QC_ERR_INTERNAL = -6
+    QC_ERR_INTERNAL = -6,
+    QC_ERR_TOO_LARGE = -7      /* the frame needs more scratch than qc_fit_noalloc holds */
 } qc_status;
 
 /* Depth sample formats.  U16: unsigned integer units of depth_scale metres (Kinect
@@ -134,6 +135,24 @@ qc_status qc_destroy(qc_context* ctx);
  * enqueue kernels on `stream` and may be captured in a HIP graph. */
 qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params,
                  const qc_output* out, void* stream);
+
+/* qc_fit for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  Same arguments, kernels and
+ * results as qc_fit (bit for bit), but the FP64 recomputation list lives in a fixed
+ * 2 MiB array of device memory that the library holds on every device it runs on
+ * (looked up by qc_create, kept until the process ends) instead of the context's
+ * scratch: the call allocates nothing, never synchronises, and only enqueues kernels on
+ * `stream` (kernel timing does not apply to it).  The array holds the lists of frames of
+ * up to 13,105 FP32-pass tiles of 256 pixels (about 3.3 Mpixels; 1280x720 needs 3,600
+ * at the default tile width); a larger frame in MIXED or FP32 precision is refused with QC_ERR_TOO_LARGE before
+ * any work is enqueued (FP64 precision uses no list and takes any size).
+ * Every call on a device shares that device's array and leaves its contents behind (the
+ * call clears what must start at zero with a kernel): calls that overlap on one device,
+ * from any context or stream, race and give undefined results, so order them on one
+ * stream (or with events).  qc_last_refit_count reports the last call's count while no
+ * later call has reused the array. */
+qc_status qc_fit_noalloc(qc_context* ctx, const qc_frame* frame, const qc_params* params,
+                         const qc_output* out, void* stream);
 
 /* One frame of a batch: its depth, parameters and outputs. */
 typedef struct {
@@ -244,8 +263,8 @@ qc_status qc_server_get_stats(qc_server* server, qc_server_stats* out);
  * are not fitted: they complete with QC_ERR_BUSY (no release can come during destruction). */
 qc_status qc_server_destroy(qc_server* server);
 
-/* Number of pixels recomputed in FP64 by the most recent qc_fit on this context
- * (MIXED), or flagged (FP32).  Synchronises with that call's stream. */
+/* Number of pixels recomputed in FP64 by the most recent qc_fit or qc_fit_noalloc on
+ * this context (MIXED), or flagged (FP32).  Synchronises with that call's stream. */
 qc_status qc_last_refit_count(qc_context* ctx, uint32_t* count);
 
 /* Kernel timing.  With timing enabled, every qc_fit on the context records HIP events

@@ -26,8 +26,9 @@ EXPORTS = ["qc_params_default", "qc_create", "qc_destroy", "qc_fit", "qc_fit_bat
            "qc_tune_save", "qc_tune_load", "qc_server_create", "qc_server_submit",
            "qc_server_poll", "qc_server_release", "qc_server_get_stats", "qc_server_destroy",
            "qc_last_refit_count", "qc_set_timing", "qc_get_timing", "qc_last_hip_error",
-           "qc_status_string"]
+           "qc_status_string", "qc_fit_noalloc"]
 QC_ERR_BUSY = -5
+QC_ERR_TOO_LARGE = -7
 QC_OUT_NORMAL, QC_OUT_RESIDUAL, QC_OUT_FLAGS = 1, 2, 4
 QC_MAX_BATCH = 256
 
@@ -123,6 +124,9 @@ def load() -> ctypes.CDLL:
     lib.qc_fit.argtypes = [vp, ctypes.POINTER(Frame), ctypes.POINTER(Params),
                            ctypes.POINTER(Output), vp]
     lib.qc_fit.restype = ctypes.c_int
+    lib.qc_fit_noalloc.argtypes = [vp, ctypes.POINTER(Frame), ctypes.POINTER(Params),
+                                   ctypes.POINTER(Output), vp]
+    lib.qc_fit_noalloc.restype = ctypes.c_int
     lib.qc_fit_batch.argtypes = [vp, ctypes.POINTER(BatchItem), ctypes.c_int32, vp]
     lib.qc_fit_batch.restype = ctypes.c_int
     lib.qc_tune.argtypes = [vp, ctypes.POINTER(Frame), ctypes.POINTER(Params), ctypes.POINTER(Output),

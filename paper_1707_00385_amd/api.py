@@ -143,6 +143,20 @@ class Context:
                                     ctypes.c_void_p(st.cuda_stream)), "qc_fit")
         return out
 
+    def fit_noalloc(self, depth: torch.Tensor, K: Sequence[float], out: Dict[str, torch.Tensor],
+                    params: Optional[_lib.Params] = None, stream: Optional[torch.cuda.Stream] = None,
+                    **param_kw) -> Dict[str, torch.Tensor]:
+        """qc_fit_noalloc: as fit(), into caller-allocated outputs `out` (make_outputs),
+        with the recomputation list in the library's fixed device scratch."""
+        if params is None:
+            params = make_params(**param_kw)
+        frame = make_frame(depth, K)
+        st = stream if stream is not None else torch.cuda.current_stream(depth.device)
+        _lib.check(self._lib.qc_fit_noalloc(self._h, ctypes.byref(frame), ctypes.byref(params),
+                                            ctypes.byref(output_struct(out)),
+                                            ctypes.c_void_p(st.cuda_stream)), "qc_fit_noalloc")
+        return out
+
     def fit_batch(self, jobs: Sequence[tuple], stream: Optional[torch.cuda.Stream] = None
                   ) -> List[Dict[str, torch.Tensor]]:
         """Fits several frames in one batched launch.  `jobs` holds (depth, K, params,

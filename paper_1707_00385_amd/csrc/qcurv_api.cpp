@@ -10,6 +10,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -55,6 +56,7 @@ struct qc_context {
     int64_t capacity = 0;
     hipStream_t last_stream = nullptr;
     int last_precision = 0;
+    const uint32_t* last_counts = nullptr;   // counters of the last fit's list (device)
     // timing: a pool of event triples created once (qc_set_timing), the triples recorded
     // and not yet read (oldest first), the free ones, and the sums of those already read
     bool timing = false;
@@ -280,6 +282,49 @@ qc_status prepare_slot(qc_context* ctx, BatchSlot& s, int64_t entries, size_t re
     return QC_OK;
 }
 
+// ---------------------------------------------------------------------------- no-alloc
+// Fixed device scratch of qc_fit_noalloc: the list counters (kCountWords words) at offset
+// 0 and the list storage from kNoAllocListOffset on, for at most kNoAllocBytes -
+// kNoAllocListOffset bytes of entries.  Every device the library runs on holds its own
+// copy until the process ends.  In host code `scratch` only names the symbol: its device
+// address comes from hipGetSymbolAddress (qc_create, once per device) and is the only one
+// ever passed to kernels or copies.
+constexpr size_t kNoAllocBytes = size_t{2} << 20;        // 2 MiB
+constexpr size_t kNoAllocListOffset = 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mutex;
+void* g_noalloc_ptr[kNoAllocDevices] = {};
+
+// Called with `device` current.  Looks up the device address of `scratch` once per device.
+hipError_t noalloc_setup(int device) {
+    if (device >= kNoAllocDevices) return hipSuccess;   // qc_fit_noalloc reports it
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (g_noalloc_ptr[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_noalloc_ptr[device] = p;
+    return e;
+}
+
+// List entries (FP32-pass tiles) whose list fits in the fixed scratch.
+int64_t noalloc_max_entries() {
+    static const int64_t n = [] {
+        const size_t avail = kNoAllocBytes - kNoAllocListOffset;
+        int64_t m = static_cast<int64_t>(avail / qc::refit_list_bytes(1));
+        while (m > 0 && qc::refit_list_bytes(m) > avail) --m;
+        return m;
+    }();
+    return n;
+}
+
+void* noalloc_ptr(int device) {
+    if (device < 0 || device >= kNoAllocDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    return g_noalloc_ptr[device];
+}
+
 }  // namespace
 
 namespace qc {
@@ -332,6 +377,12 @@ qc_status qc_create(qc_context** out, int device) {
     }
     ctx->cus = cus > 0 ? cus : 1;
     ctx->refit_counts = static_cast<uint32_t*>(p);
+    if ((e = noalloc_setup(device)) != hipSuccess) {
+        (void)hipFree(p);
+        (void)hipStreamDestroy(ctx->capture_stream);
+        delete ctx;
+        return QC_ERR_HIP;
+    }
     *out = ctx;
     return QC_OK;
 }
@@ -375,6 +426,33 @@ qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params
     if ((e = qc::launch_fit(d, list, ctx->cus, s, ev)) != hipSuccess) return hip_fail(ctx, e);
     ctx->last_stream = s;
     ctx->last_precision = params->precision;
+    ctx->last_counts = ctx->refit_counts;
+    return QC_OK;
+}
+
+qc_status qc_fit_noalloc(qc_context* ctx, const qc_frame* frame, const qc_params* params,
+                         const qc_output* out, void* stream) {
+    if (!ctx) return QC_ERR_INVALID_ARG;
+    qc_status st;
+    if ((st = check_frame(frame)) != QC_OK) return st;
+    if ((st = check_params(params)) != QC_OK) return st;
+    if (!out || !out->k1 || !out->k2) return QC_ERR_INVALID_ARG;
+    const int tw = tile_width_for(ctx, frame, params);
+    const int64_t entries = qc::refit_capacity(frame->width, frame->height, tw);
+    const int64_t max_entries = noalloc_max_entries();
+    if (params->precision != QC_PREC_FP64 && entries > max_entries) return QC_ERR_TOO_LARGE;
+    unsigned char* base = static_cast<unsigned char*>(noalloc_ptr(ctx->device));
+    if (!base) return QC_ERR_UNSUPPORTED;
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
+    const qc::FitDesc d = make_desc(frame, params, out, tw);
+    uint32_t* counts = reinterpret_cast<uint32_t*>(base);
+    const qc::RefitList list = qc::refit_list(base + kNoAllocListOffset, max_entries, counts);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((e = qc::launch_fit(d, list, ctx->cus, s, nullptr)) != hipSuccess) return hip_fail(ctx, e);
+    ctx->last_stream = s;
+    ctx->last_precision = params->precision;
+    ctx->last_counts = counts;
     return QC_OK;
 }
 
@@ -535,7 +613,8 @@ qc_status qc_last_refit_count(qc_context* ctx, uint32_t* count) {
     if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
     if ((e = hipStreamSynchronize(ctx->last_stream)) != hipSuccess) return hip_fail(ctx, e);
     uint32_t counts[qc::kCountWords] = {};
-    if ((e = hipMemcpy(counts, ctx->refit_counts, sizeof counts, hipMemcpyDeviceToHost)) != hipSuccess)
+    const uint32_t* src = ctx->last_counts ? ctx->last_counts : ctx->refit_counts;
+    if ((e = hipMemcpy(counts, src, sizeof counts, hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(ctx, e);
     *count = counts[4];   // listed pixels
     return QC_OK;
@@ -585,6 +664,7 @@ const char* qc_status_string(qc_status s) {
         case QC_ERR_HIP: return "HIP runtime error";
         case QC_ERR_BUSY: return "busy";
         case QC_ERR_INTERNAL: return "internal error";
+        case QC_ERR_TOO_LARGE: return "frame too large for the fixed scratch of qc_fit_noalloc";
     }
     return "unknown status";
 }

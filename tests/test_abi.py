@@ -37,7 +37,7 @@ def test_defaults_and_status_strings():
     assert p.k == pytest.approx(1e-5) and p.depth_scale == pytest.approx(1e-3)
     assert p.precision == _lib.QC_PREC_MIXED and p.reject == 0 and p.stride == 1
     assert p.cond_max == pytest.approx(15.0) and p.step_max == pytest.approx(0.1)
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.qc_status_string(code)
     assert lib.qc_status_string(12345) == b"unknown status"
 
@@ -45,6 +45,7 @@ def test_defaults_and_status_strings():
 def test_null_arguments_rejected_without_a_device():
     lib = _lib.load()
     assert lib.qc_fit(None, None, None, None, None) == -1
+    assert lib.qc_fit_noalloc(None, None, None, None, None) == -1
     assert lib.qc_create(None, 0) == -1
     assert lib.qc_destroy(None) == 0
     assert lib.qc_last_hip_error(None) == 0
