@@ -344,46 +344,80 @@ def measure_served(ctx, duration_s: float = 4.0, fps: float = 240.0, sensors: in
     return res
 
 
-def measure_batched(ctx, reps: int = 5) -> dict:
+def measure_batched(ctx, reps: int = 5, tune_reps: int = 3) -> dict:
     """The batched form: 64 frames in equal thirds of 512x424 ToF-like, 640x480 and
     1280x720 depth, window radius from {3, 5, 7, 11}, iterations from {3, 5} (seeded), fitted
     by one qc_fit_batch call (persistent launches replayed from a graph) and, for
-    comparison, by 64 qc_fit calls.  Three rendered frames per sensor kind are shared by the
-    64 items; every item has its own outputs."""
+    comparison, by 64 qc_fit calls; first with the default tile width (16) and schedule
+    (MIXED), then on a second context after qc_tune has recorded a tile width and schedule
+    for each (size, radius, iterations) of the mix (the table is saved with qc_tune_save
+    and loaded back, as a deployment would).  Three rendered frames per sensor kind are
+    shared by the 64 items; every item has its own outputs."""
+    import tempfile
     import torch
     from paper_1707_00385_amd import scenes
-    from paper_1707_00385_amd.api import make_outputs, make_params, upload_depth
+    from paper_1707_00385_amd.api import Context, make_outputs, make_params, upload_depth
     mix = scenes.batch_mix(64, seed=0)
     pool = {k: (upload_depth(d, "u16"), cam) for k, (d, cam) in sensor_pool().items()}
-    jobs, pixels, flops = [], 0, 0.0
+    jobs, pixels = [], 0
+    configs = {}
     for i, m in enumerate(mix):
         t, cam = pool[(m["kind"], i % 3)]
         p = make_params(radius=m["radius"], iterations=m["iterations"])
         o = make_outputs(t.shape[0], t.shape[1], t.device, flags=False)
         jobs.append((t, (cam.fx, cam.fy, cam.cx, cam.cy), p, o))
         pixels += t.shape[0] * t.shape[1]
-    ctx.fit_batch(jobs)
-    for t, K, p, o in jobs:
-        ctx.fit(t, K, params=p, out=o)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        ctx.fit_batch(jobs)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / reps
-    t0 = time.perf_counter()
-    for _ in range(reps):
+        configs.setdefault((m["kind"], m["radius"], m["iterations"]), (t, (cam.fx, cam.fy, cam.cx, cam.cy), p))
+
+    def timed(c):
+        c.fit_batch(jobs)
         for t, K, p, o in jobs:
-            ctx.fit(t, K, params=p, out=o)
-    torch.cuda.synchronize()
-    t_single = (time.perf_counter() - t0) / reps
-    return {"frames": len(jobs), "pixels_per_batch": pixels,
-            "batched": {"ms_per_batch": round(1e3 * t_batch, 3), "pixels_per_s": round(pixels / t_batch, 1)},
-            "per_frame_launches": {"ms_per_batch": round(1e3 * t_single, 3),
-                                   "pixels_per_s": round(pixels / t_single, 1)},
-            "speedup": round(t_single / t_batch, 3),
-            "mix": "64 frames: 1/3 each 512x424 ToF (sigma=1e-3 Z), 640x480 and 1280x720 "
-                   "Kinect-like u16; r in {3,5,7,11}, T in {3,5}, seeded"}
+            c.fit(t, K, params=p, out=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c.fit_batch(jobs)
+        torch.cuda.synchronize()
+        t_batch = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for t, K, p, o in jobs:
+                c.fit(t, K, params=p, out=o)
+        torch.cuda.synchronize()
+        t_single = (time.perf_counter() - t0) / reps
+        return {"batched": {"ms_per_batch": round(1e3 * t_batch, 3), "pixels_per_s": round(pixels / t_batch, 1)},
+                "per_frame_launches": {"ms_per_batch": round(1e3 * t_single, 3),
+                                       "pixels_per_s": round(pixels / t_single, 1)},
+                "speedup": round(t_single / t_batch, 3)}
+
+    res = {"frames": len(jobs), "pixels_per_batch": pixels}
+    res.update(timed(ctx))
+    tuned_ctx = Context(0)
+    try:
+        t0 = time.perf_counter()
+        table = []
+        for (kind, r, T), (t, K, p) in sorted(configs.items()):
+            tw, sched = tuned_ctx.tune(t, K, p, reps=tune_reps, with_schedule=True)
+            table.append({"sensor": kind, "size": f"{t.shape[1]}x{t.shape[0]}", "radius": r, "iterations": T,
+                          "tile_width": tw, "schedule": {0: "mixed", 2: "fp64"}.get(sched, str(sched))})
+        tune_s = time.perf_counter() - t0
+        with tempfile.TemporaryDirectory() as d:
+            path = os.path.join(d, "tune.txt")
+            tuned_ctx.tune_save(path)
+            fresh = Context(0)
+            try:
+                fresh.tune_load(path)
+                tuned = timed(fresh)
+            finally:
+                fresh.close()
+    finally:
+        tuned_ctx.close()
+    res["tuned"] = dict(tuned, tuning_seconds=round(tune_s, 2), table=table,
+                        speedup_over_untuned_batch=round(res["batched"]["ms_per_batch"] /
+                                                         tuned["batched"]["ms_per_batch"], 3))
+    res["mix"] = ("64 frames: 1/3 each 512x424 ToF (sigma=1e-3 Z), 640x480 and 1280x720 "
+                  "Kinect-like u16; r in {3,5,7,11}, T in {3,5}, seeded")
+    return res
 
 
 def measure_precision_modes(ctx, dev, K, steps: int = 100) -> dict:
@@ -451,38 +485,49 @@ PAPER_PATCHES = ((4, 1, "9x9"), (10, 1, "21x21"), (18, 3, "37x37 every 3rd pixel
 
 
 def measure_paper_grid(ctx, steps: int = 50) -> list:
-    """The paper's timing grid on this GPU: three image sizes x three patches (T = 5,
-    MIXED), one seeded cluttered u16 frame per size, per-frame launches."""
+    """The paper's timing grid on this GPU: three image sizes x three patches (T = 5), one
+    seeded cluttered u16 frame per size, per-frame launches: MIXED with the default tile
+    width, FP64 throughout, and MIXED after qc_tune (on a context of its own) has recorded
+    the cell's tile width and schedule."""
     import torch
     from paper_1707_00385_amd import scenes
-    from paper_1707_00385_amd.api import make_outputs, make_params, upload_depth
+    from paper_1707_00385_amd.api import Context, make_outputs, make_params, upload_depth
     cams = {(640, 480): scenes.CAM_VGA, (512, 424): scenes.CAM_TOF,
             (320, 240): scenes.Camera(320, 240, 262.5, 262.5, 159.5, 119.5)}
     rows = []
-    for (w, h), cam in cams.items():
-        sc = scenes.cluttered_scene(cam, seed_frame=0, config_index=10)
-        t = upload_depth(sc.depth_u16(), "u16")
-        K = (cam.fx, cam.fy, cam.cx, cam.cy)
-        out = make_outputs(h, w, t.device, flags=False)
-        for j, (r, stride, label) in enumerate(PAPER_PATCHES):
-            def timed(p):
-                for _ in range(5):
-                    ctx.fit(t, K, params=p, out=out)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(steps):
-                    ctx.fit(t, K, params=p, out=out)
-                torch.cuda.synchronize()
-                return 1e3 * (time.perf_counter() - t0) / steps
-            p = make_params(radius=r, iterations=ITERS, k=K_ROBUST, stride=stride)
-            ms = timed(p)
-            ctx.fit(t, K, params=p, out=out)
-            refit = ctx.last_refit_count() / (w * h)
-            ms64 = timed(make_params(radius=r, iterations=ITERS, k=K_ROBUST, stride=stride, precision="fp64"))
-            rows.append({"image": f"{w}x{h}", "patch": label, "radius": r, "stride": stride,
-                         "ms_per_frame": round(ms, 4), "pixels_per_s": round(w * h / ms * 1e3, 1),
-                         "refit_fraction": round(refit, 4), "fp64_mode_ms_per_frame": round(ms64, 4),
-                         "paper_k40c_ms": PAPER_GRID_MS[(w, h)][j]})
+    tuned_ctx = Context(0)
+    try:
+        for (w, h), cam in cams.items():
+            sc = scenes.cluttered_scene(cam, seed_frame=0, config_index=10)
+            t = upload_depth(sc.depth_u16(), "u16")
+            K = (cam.fx, cam.fy, cam.cx, cam.cy)
+            out = make_outputs(h, w, t.device, flags=False)
+            for j, (r, stride, label) in enumerate(PAPER_PATCHES):
+                def timed(c, p):
+                    for _ in range(5):
+                        c.fit(t, K, params=p, out=out)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(steps):
+                        c.fit(t, K, params=p, out=out)
+                    torch.cuda.synchronize()
+                    return 1e3 * (time.perf_counter() - t0) / steps
+                p = make_params(radius=r, iterations=ITERS, k=K_ROBUST, stride=stride)
+                ms = timed(ctx, p)
+                ctx.fit(t, K, params=p, out=out)
+                refit = ctx.last_refit_count() / (w * h)
+                ms64 = timed(ctx, make_params(radius=r, iterations=ITERS, k=K_ROBUST, stride=stride,
+                                              precision="fp64"))
+                tw, sched = tuned_ctx.tune(t, K, p, reps=5, with_schedule=True)
+                ms_tuned = timed(tuned_ctx, p)
+                rows.append({"image": f"{w}x{h}", "patch": label, "radius": r, "stride": stride,
+                             "ms_per_frame": round(ms, 4), "pixels_per_s": round(w * h / ms * 1e3, 1),
+                             "refit_fraction": round(refit, 4), "fp64_mode_ms_per_frame": round(ms64, 4),
+                             "tuned": {"tile_width": tw, "schedule": {0: "mixed", 2: "fp64"}.get(sched, str(sched)),
+                                       "ms_per_frame": round(ms_tuned, 4)},
+                             "paper_k40c_ms": PAPER_GRID_MS[(w, h)][j]})
+    finally:
+        tuned_ctx.close()
     return rows
 
 

@@ -90,8 +90,9 @@ typedef struct {
                                 h_w = r Z / fx the window half-extent at the pixel; for
                                 r > 7 (any stride) the bound applied is step_max * (7/r)^2 */
     int32_t tile_width;      /* FP32 pass tile: 8, 16, 32 or 64 pixels wide (256 pixels);
-                                0 = the width qc_tune recorded for this frame size, radius
-                                and iteration count, else 16.  Results do not depend on it. */
+                                0 = the width (and, for MIXED, the schedule) qc_tune
+                                recorded for this configuration, else 16 and MIXED.  Results
+                                do not depend on the width. */
     int32_t stride;          /* 1..radius: the fit window takes the pixels at offsets that
                                 are multiples of `stride` within +-radius (the sparsely
                                 sampled large patch of the timings of Section 4), i.e.
@@ -175,15 +176,25 @@ typedef struct {
  * `stream`; the items array itself may be reused as soon as the call returns. */
 qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, void* stream);
 
-/* Autotuning of the FP32 tile shape: runs qc_fit on `frame` with each tile width (8, 16,
- * 32, 64), `reps` times each, timed with HIP events on `stream`, writing into `out`
- * (whose contents are then undefined), and records the fastest width for frames of that
- * size, radius and iteration count; `tile_width` (may be NULL) receives it.  Synchronous. */
+/* Autotuning of a frame configuration (size, radius, iterations, stride, reject): runs
+ * qc_fit on `frame` with each FP32-pass tile width (8, 16, 32, 64) and, for a MIXED
+ * request, also in FP64 throughout, `reps` times each after one warm-up call, timed with
+ * HIP events on `stream`, writing into `out` (whose contents are then undefined).  It
+ * records the fastest tile width and the schedule of MIXED requests for that
+ * configuration: QC_PREC_MIXED (the FP32 pass plus the FP64 recomputation of the pixels
+ * it lists) or QC_PREC_FP64 (every pixel in FP64: more accurate, and faster where the FP32
+ * pass would list many pixels).  Later requests of that configuration with tile_width 0
+ * use the recorded width, and MIXED ones the recorded schedule (their flags then mark
+ * every fitted pixel QC_FLAG_FP64; qc_fit_batch runs such items as per-frame FP64
+ * launches).  `tile_width` and `schedule` (either may be NULL) receive them.  Synchronous. */
 qc_status qc_tune(qc_context* ctx, const qc_frame* frame, const qc_params* params,
-                  const qc_output* out, int32_t reps, void* stream, int32_t* tile_width);
+                  const qc_output* out, int32_t reps, void* stream, int32_t* tile_width,
+                  int32_t* schedule);
 
-/* Saves / loads the recorded tile widths as text lines "width height radius iterations
- * tile_width" (load merges into the context's table). */
+/* Saves / loads the recorded configurations as text lines "width height radius
+ * iterations stride reject tile_width schedule" (load also accepts the older five-field
+ * lines "width height radius iterations tile_width", and merges into the context's table;
+ * a malformed file changes nothing and returns QC_ERR_INVALID_ARG). */
 qc_status qc_tune_save(qc_context* ctx, const char* path);
 qc_status qc_tune_load(qc_context* ctx, const char* path);
 

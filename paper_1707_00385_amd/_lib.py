@@ -130,7 +130,7 @@ def load() -> ctypes.CDLL:
     lib.qc_fit_batch.argtypes = [vp, ctypes.POINTER(BatchItem), ctypes.c_int32, vp]
     lib.qc_fit_batch.restype = ctypes.c_int
     lib.qc_tune.argtypes = [vp, ctypes.POINTER(Frame), ctypes.POINTER(Params), ctypes.POINTER(Output),
-                            ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32)]
+                            ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.qc_tune.restype = ctypes.c_int
     lib.qc_tune_save.argtypes = [vp, ctypes.c_char_p]
     lib.qc_tune_save.restype = ctypes.c_int

@@ -181,16 +181,18 @@ class Context:
         return outs
 
     def tune(self, depth: torch.Tensor, K: Sequence[float], params: _lib.Params, reps: int = 5,
-             stream: Optional[torch.cuda.Stream] = None) -> int:
-        """Times the FP32 tile shapes on this frame and records the fastest; returns it."""
+             stream: Optional[torch.cuda.Stream] = None, with_schedule: bool = False):
+        """qc_tune: times the FP32 tile shapes (and, for MIXED, FP64 throughout) on this
+        frame and records the fastest; returns the tile width, or (tile width, schedule)."""
         frame = make_frame(depth, K)
         out = make_outputs(frame.height, frame.width, depth.device)
         st = stream if stream is not None else torch.cuda.current_stream(depth.device)
-        tw = ctypes.c_int32()
+        tw, sched = ctypes.c_int32(), ctypes.c_int32()
         _lib.check(self._lib.qc_tune(self._h, ctypes.byref(frame), ctypes.byref(params),
                                      ctypes.byref(output_struct(out)), int(reps),
-                                     ctypes.c_void_p(st.cuda_stream), ctypes.byref(tw)), "qc_tune")
-        return int(tw.value)
+                                     ctypes.c_void_p(st.cuda_stream), ctypes.byref(tw),
+                                     ctypes.byref(sched)), "qc_tune")
+        return (int(tw.value), int(sched.value)) if with_schedule else int(tw.value)
 
     def tune_save(self, path: str) -> None:
         _lib.check(self._lib.qc_tune_save(self._h, path.encode()), "qc_tune_save")

@@ -43,7 +43,19 @@ struct BatchSlot {
     bool in_flight = false;
 };
 
-using TuneKey = std::tuple<int, int, int, int>;   // width, height, radius, iterations
+// width, height, radius, iterations, stride, reject
+using TuneKey = std::tuple<int, int, int, int, int, int>;
+// What qc_tune recorded for a key: the FP32 pass's tile width, and the schedule of a MIXED
+// request: QC_PREC_MIXED (the FP32 pass plus the FP64 recomputation of listed pixels) or
+// QC_PREC_FP64 (every pixel in FP64, where that measured faster).
+struct TuneEntry {
+    int tile_width = 16;
+    int schedule = QC_PREC_MIXED;
+};
+
+TuneKey tune_key(const qc_frame* f, const qc_params* p) {
+    return TuneKey{f->width, f->height, p->radius, p->iterations, p->stride, p->reject};
+}
 
 }  // namespace
 
@@ -67,8 +79,8 @@ struct qc_context {
     BatchSlot slots[2];
     int next_slot = 0;
     hipStream_t capture_stream = nullptr;
-    // tuned FP32 tile widths
-    std::map<TuneKey, int> tuned;
+    // tuned tile widths and schedules
+    std::map<TuneKey, TuneEntry> tuned;
 };
 
 namespace {
@@ -163,8 +175,17 @@ int64_t max_tiles(int width, int height) {
 
 int tile_width_for(const qc_context* ctx, const qc_frame* f, const qc_params* p) {
     if (p->tile_width != 0) return p->tile_width;
-    auto it = ctx->tuned.find(TuneKey{f->width, f->height, p->radius, p->iterations});
-    return it != ctx->tuned.end() ? it->second : 16;
+    auto it = ctx->tuned.find(tune_key(f, p));
+    return it != ctx->tuned.end() ? it->second.tile_width : 16;
+}
+
+// The precision a request runs at: a MIXED request with tile_width 0 takes the schedule
+// qc_tune recorded for its key (FP64 throughout where that measured faster); any other
+// request runs as asked.
+int32_t precision_for(const qc_context* ctx, const qc_frame* f, const qc_params* p) {
+    if (p->precision != QC_PREC_MIXED || p->tile_width != 0) return p->precision;
+    auto it = ctx->tuned.find(tune_key(f, p));
+    return it != ctx->tuned.end() ? it->second.schedule : QC_PREC_MIXED;
 }
 
 qc::FitDesc make_desc(const qc_frame* frame, const qc_params* params, const qc_output* out,
@@ -415,17 +436,19 @@ qc_status qc_fit(qc_context* ctx, const qc_frame* frame, const qc_params* params
     if (!out || !out->k1 || !out->k2) return QC_ERR_INVALID_ARG;
     hipError_t e;
     if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
-    if (params->precision != QC_PREC_FP64 &&
+    qc_params p = *params;
+    p.precision = precision_for(ctx, frame, params);
+    if (p.precision != QC_PREC_FP64 &&
         (st = ensure_capacity(ctx, max_tiles(frame->width, frame->height))) != QC_OK)
         return st;
-    const qc::FitDesc d = make_desc(frame, params, out, tile_width_for(ctx, frame, params));
+    const qc::FitDesc d = make_desc(frame, &p, out, tile_width_for(ctx, frame, params));
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t* ev = nullptr;
     if ((st = next_triple(ctx, &ev)) != QC_OK) return st;
     const qc::RefitList list = qc::refit_list(ctx->refit_storage, ctx->capacity, ctx->refit_counts);
     if ((e = qc::launch_fit(d, list, ctx->cus, s, ev)) != hipSuccess) return hip_fail(ctx, e);
     ctx->last_stream = s;
-    ctx->last_precision = params->precision;
+    ctx->last_precision = p.precision;
     ctx->last_counts = ctx->refit_counts;
     return QC_OK;
 }
@@ -438,20 +461,22 @@ qc_status qc_fit_noalloc(qc_context* ctx, const qc_frame* frame, const qc_params
     if ((st = check_params(params)) != QC_OK) return st;
     if (!out || !out->k1 || !out->k2) return QC_ERR_INVALID_ARG;
     const int tw = tile_width_for(ctx, frame, params);
+    qc_params p = *params;
+    p.precision = precision_for(ctx, frame, params);
     const int64_t entries = qc::refit_capacity(frame->width, frame->height, tw);
     const int64_t max_entries = noalloc_max_entries();
-    if (params->precision != QC_PREC_FP64 && entries > max_entries) return QC_ERR_TOO_LARGE;
+    if (p.precision != QC_PREC_FP64 && entries > max_entries) return QC_ERR_TOO_LARGE;
     unsigned char* base = static_cast<unsigned char*>(noalloc_ptr(ctx->device));
     if (!base) return QC_ERR_UNSUPPORTED;
     hipError_t e;
     if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
-    const qc::FitDesc d = make_desc(frame, params, out, tw);
+    const qc::FitDesc d = make_desc(frame, &p, out, tw);
     uint32_t* counts = reinterpret_cast<uint32_t*>(base);
     const qc::RefitList list = qc::refit_list(base + kNoAllocListOffset, max_entries, counts);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((e = qc::launch_fit(d, list, ctx->cus, s, nullptr)) != hipSuccess) return hip_fail(ctx, e);
     ctx->last_stream = s;
-    ctx->last_precision = params->precision;
+    ctx->last_precision = p.precision;
     ctx->last_counts = counts;
     return QC_OK;
 }
@@ -473,10 +498,32 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
     if (prec == QC_PREC_FP64) return QC_ERR_UNSUPPORTED;
     hipError_t e;
     if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(ctx, e);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+
+    // Items whose tuned schedule is FP64 throughout run as per-frame FP64 launches (which
+    // use no list); the others form the batch.
+    std::vector<int32_t> batched;
+    std::vector<qc::FitDesc> fp64_descs;
+    for (int32_t i = 0; i < n; ++i) {
+        const qc_batch_item& it = items[i];
+        if (precision_for(ctx, &it.frame, &it.params) == QC_PREC_FP64) {
+            qc_params p = it.params;
+            p.precision = QC_PREC_FP64;
+            fp64_descs.push_back(make_desc(&it.frame, &p, &it.out, tile_width_for(ctx, &it.frame, &it.params)));
+        } else {
+            batched.push_back(i);
+        }
+    }
+    if (!fp64_descs.empty()) {
+        const qc::RefitList none = qc::refit_list(nullptr, 0, ctx->refit_counts);
+        for (const qc::FitDesc& d : fp64_descs)
+            if ((e = qc::launch_fit(d, none, ctx->cus, hs)) != hipSuccess) return hip_fail(ctx, e);
+    }
+    n = static_cast<int32_t>(batched.size());
+    if (n == 0) return QC_OK;
 
     // frames from most to least work per tile, so the long tiles start first
-    std::vector<int32_t> order(n);
-    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    std::vector<int32_t> order(batched);
     auto cost = [&](int32_t i) {
         const int r = items[i].params.radius;
         return static_cast<int64_t>(2 * r + 1) * (2 * r + 1) * std::max(1, items[i].params.iterations);
@@ -504,7 +551,6 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
     std::memcpy(s.host->frames, descs.data(), sizeof(qc::FitDesc) * n);
     std::memcpy(s.host->first_tile, first.data(), sizeof(uint32_t) * (n + 1));
     s.host->header[0] = static_cast<uint32_t>(n);
-    hipStream_t hs = static_cast<hipStream_t>(stream);
     if (per_frame) {
         // The batched kernels carry only the default weights of Eq. (11) and dense
         // windows: a batch holding rejection or strided frames runs as per-frame launches,
@@ -532,7 +578,8 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
 }
 
 qc_status qc_tune(qc_context* ctx, const qc_frame* frame, const qc_params* params,
-                  const qc_output* out, int32_t reps, void* stream, int32_t* tile_width) {
+                  const qc_output* out, int32_t reps, void* stream, int32_t* tile_width,
+                  int32_t* schedule) {
     if (!ctx || reps < 1) return QC_ERR_INVALID_ARG;
     qc_status st;
     if ((st = check_frame(frame)) != QC_OK) return st;
@@ -548,30 +595,44 @@ qc_status qc_tune(qc_context* ctx, const qc_frame* frame, const qc_params* param
     }
     const bool timing = ctx->timing;
     ctx->timing = false;
-    int best = 16;
+    // milliseconds of `reps` fits with parameters p (after one warm-up fit)
+    auto time_fits = [&](const qc_params& p, float* ms) {
+        qc_status r = qc_fit(ctx, frame, &p, out, stream);
+        if (r == QC_OK && (e = hipEventRecord(a, s)) != hipSuccess) r = hip_fail(ctx, e);
+        for (int32_t i = 0; i < reps && r == QC_OK; ++i) r = qc_fit(ctx, frame, &p, out, stream);
+        if (r == QC_OK && ((e = hipEventRecord(b, s)) != hipSuccess || (e = hipEventSynchronize(b)) != hipSuccess ||
+                           (e = hipEventElapsedTime(ms, a, b)) != hipSuccess))
+            r = hip_fail(ctx, e);
+        return r;
+    };
+    TuneEntry best;
     float best_ms = 0.f;
     for (int tw = 8; tw <= 64 && st == QC_OK; tw *= 2) {
         qc_params p = *params;
-        p.tile_width = tw;
-        st = qc_fit(ctx, frame, &p, out, stream);   // warm-up
-        if (st == QC_OK && (e = hipEventRecord(a, s)) != hipSuccess) st = hip_fail(ctx, e);
-        for (int32_t i = 0; i < reps && st == QC_OK; ++i) st = qc_fit(ctx, frame, &p, out, stream);
+        p.tile_width = tw;   // an explicit width: the fit runs at the requested precision
         float ms = 0.f;
-        if (st == QC_OK && ((e = hipEventRecord(b, s)) != hipSuccess ||
-                            (e = hipEventSynchronize(b)) != hipSuccess ||
-                            (e = hipEventElapsedTime(&ms, a, b)) != hipSuccess))
-            st = hip_fail(ctx, e);
+        st = time_fits(p, &ms);
         if (st == QC_OK && (tw == 8 || ms < best_ms)) {
-            best = tw;
+            best.tile_width = tw;
             best_ms = ms;
         }
+    }
+    if (st == QC_OK && params->precision == QC_PREC_MIXED) {
+        // the other schedule of a MIXED request: every pixel in FP64 (more accurate, and
+        // faster where the FP32 pass would list many pixels for recomputation)
+        qc_params p = *params;
+        p.precision = QC_PREC_FP64;
+        float ms = 0.f;
+        st = time_fits(p, &ms);
+        if (st == QC_OK && ms < best_ms) best.schedule = QC_PREC_FP64;
     }
     ctx->timing = timing;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (st != QC_OK) return st;
-    ctx->tuned[TuneKey{frame->width, frame->height, params->radius, params->iterations}] = best;
-    if (tile_width) *tile_width = best;
+    ctx->tuned[tune_key(frame, params)] = best;
+    if (tile_width) *tile_width = best.tile_width;
+    if (schedule) *schedule = best.schedule;
     return QC_OK;
 }
 
@@ -580,8 +641,9 @@ qc_status qc_tune_save(qc_context* ctx, const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return QC_ERR_INVALID_ARG;
     for (const auto& kv : ctx->tuned)
-        std::fprintf(f, "%d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
-                     std::get<2>(kv.first), std::get<3>(kv.first), kv.second);
+        std::fprintf(f, "%d %d %d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                     std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first),
+                     std::get<5>(kv.first), kv.second.tile_width, kv.second.schedule);
     return std::fclose(f) == 0 ? QC_OK : QC_ERR_INVALID_ARG;
 }
 
@@ -589,20 +651,37 @@ qc_status qc_tune_load(qc_context* ctx, const char* path) {
     if (!ctx || !path) return QC_ERR_INVALID_ARG;
     FILE* f = std::fopen(path, "r");
     if (!f) return QC_ERR_INVALID_ARG;
-    int w, h, r, t, tw;
+    char line[256];
     qc_status st = QC_OK;
-    while (true) {
-        const int got = std::fscanf(f, "%d %d %d %d %d", &w, &h, &r, &t, &tw);
-        if (got == EOF) break;
-        if (got != 5 || w < 1 || h < 1 || r < 1 || r > QC_MAX_RADIUS || t < 0 ||
-            !qc::valid_tile_width(tw)) {
+    std::map<TuneKey, TuneEntry> got;
+    while (std::fgets(line, sizeof line, f)) {
+        int w, h, r, t, stride = 1, reject = 0, tw, sched = QC_PREC_MIXED;
+        char extra;
+        const int n = std::sscanf(line, "%d %d %d %d %d %d %d %d %c", &w, &h, &r, &t, &stride, &reject, &tw,
+                                  &sched, &extra);
+        if (n == EOF) continue;   // blank line
+        if (n == 5) {             // "width height radius iterations tile_width"
+            tw = stride;
+            stride = 1;
+        } else if (n != 8) {
             st = QC_ERR_INVALID_ARG;
             break;
         }
-        ctx->tuned[TuneKey{w, h, r, t}] = tw;
+        if (w < 1 || h < 1 || r < 1 || r > QC_MAX_RADIUS || t < 0 || stride < 1 || stride > r ||
+            (reject != 0 && reject != 1) || !qc::valid_tile_width(tw) ||
+            (sched != QC_PREC_MIXED && sched != QC_PREC_FP64)) {
+            st = QC_ERR_INVALID_ARG;
+            break;
+        }
+        TuneEntry e;
+        e.tile_width = tw;
+        e.schedule = sched;
+        got[TuneKey{w, h, r, t, stride, reject}] = e;
     }
     std::fclose(f);
-    return st;
+    if (st != QC_OK) return st;   // a malformed file changes nothing
+    for (const auto& kv : got) ctx->tuned[kv.first] = kv.second;
+    return QC_OK;
 }
 
 qc_status qc_last_refit_count(qc_context* ctx, uint32_t* count) {

@@ -174,19 +174,72 @@ def test_batch_against_oracle(ctx):
 
 
 def test_tune_records_and_round_trips(ctx):
+    """qc_tune records a tile width and a schedule for the frame's configuration; the
+    saved table has one line "width height radius iterations stride reject tile_width
+    schedule", loads back, and the older five-field line loads too."""
+    from paper_1707_00385_amd import _lib
     from paper_1707_00385_amd.api import make_params, upload_depth
     sc = scenes.cluttered_scene(scenes.Camera(128, 96, 100.0, 100.0, 63.5, 47.5), seed_frame=9,
                                 config_index=8)
     t = upload_depth(sc.depth_u16(), "u16")
     K = (sc.camera.fx, sc.camera.fy, sc.camera.cx, sc.camera.cy)
-    tw = ctx.tune(t, K, make_params(radius=3, iterations=3), reps=2)
-    assert tw in (8, 16, 32, 64)
+    tw, sched = ctx.tune(t, K, make_params(radius=3, iterations=3), reps=2, with_schedule=True)
+    assert tw in (8, 16, 32, 64) and sched in (_lib.QC_PREC_MIXED, _lib.QC_PREC_FP64)
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "tune.txt")
         ctx.tune_save(path)
         line = open(path).read().split()
-        assert line == ["128", "96", "3", "3", str(tw)]
+        assert line == ["128", "96", "3", "3", "1", "0", str(tw), str(sched)]
         ctx.tune_load(path)
+        legacy = os.path.join(d, "legacy.txt")
+        with open(legacy, "w") as f:
+            f.write("64 48 5 5 32\n")
+        ctx.tune_load(legacy)
+        bad = os.path.join(d, "bad.txt")
+        with open(bad, "w") as f:
+            f.write("64 48 5 5 1 0 32 1\n")   # schedule FP32 is not a schedule
+        with pytest.raises(_lib.QcError):
+            ctx.tune_load(bad)
+
+
+def test_tuned_fp64_schedule_runs_fp64_alone_and_in_batches():
+    """A configuration whose recorded schedule is FP64 throughout: a MIXED request with
+    tile_width 0 runs every pixel in FP64 (flags say so) and gives the FP64-precision
+    request's results bit for bit; in a batch beside ordinary MIXED items each item
+    equals its per-frame call."""
+    import torch
+    from paper_1707_00385_amd import _lib
+    from paper_1707_00385_amd.api import Context, make_outputs, make_params, upload_depth
+    c = Context(0)
+    try:
+        cam_a = scenes.Camera(96, 72, 80.0, 80.0, 47.5, 35.5)
+        cam_b = scenes.Camera(100, 75, 90.0, 90.0, 49.5, 37.0)
+        ta = upload_depth(scenes.cluttered_scene(cam_a, seed_frame=70, config_index=3).depth_u16(), "u16")
+        tb = upload_depth(scenes.cluttered_scene(cam_b, seed_frame=71, config_index=3).depth_u16(), "u16")
+        with tempfile.TemporaryDirectory() as d:
+            path = os.path.join(d, "tune.txt")
+            with open(path, "w") as f:
+                f.write("96 72 4 3 1 0 16 2\n")   # 96x72, r = 4, T = 3: FP64 throughout
+            c.tune_load(path)
+        log("[case] tuned FP64 schedule, per frame and in a batch")
+        mixed = make_params(radius=4, iterations=3)
+        got = _run_single(c, ta, cam_a, mixed)
+        valid = (got["flags"] & _lib.QC_FLAG_VALID) != 0
+        assert valid.any() and np.all((got["flags"][valid] & _lib.QC_FLAG_FP64) != 0)
+        fp64 = _run_single(c, ta, cam_a, make_params(radius=4, iterations=3, precision="fp64"))
+        for k in KEYS:
+            assert np.array_equal(got[k], fp64[k], equal_nan=True), k
+        jobs = [(ta, cam_a), (tb, cam_b), (ta, cam_a)]
+        bj = [(t, (cam.fx, cam.fy, cam.cx, cam.cy), mixed,
+               make_outputs(cam.height, cam.width, t.device, normal=True, residual=True)) for t, cam in jobs]
+        outs = c.fit_batch(bj)
+        torch.cuda.synchronize()
+        for (t, cam), o in zip(jobs, outs):
+            single = _run_single(c, t, cam, mixed)
+            for k in KEYS:
+                assert np.array_equal(o[k].cpu().numpy(), single[k], equal_nan=True), k
+    finally:
+        c.close()
 
 
 def test_batches_needing_more_lds_recapture():
