@@ -19,13 +19,28 @@ hipError_t launch_frame_strided_reject(const FitDesc& d, const RefitList& list, 
 
 namespace {
 
+// The tile a workgroup of a per-frame pass fits.  Workgroups are dispatched to the eight
+// XCDs in turn (workgroup w to XCD w mod 8), each XCD with its own L2; the tiles are dealt
+// out so that XCD x takes the x-th contiguous eighth of the frame's tiles in row-major
+// order, and neighbouring tiles, which stage overlapping halos, mostly share an L2.  A
+// bijection of [0, tiles): results do not depend on it.
+__device__ __forceinline__ int2 xcd_tile() {
+    constexpr uint32_t kXcds = 8;
+    const uint32_t n = gridDim.x * gridDim.y;
+    const uint32_t w = blockIdx.y * gridDim.x + blockIdx.x;
+    const uint32_t x = w % kXcds, k = w / kXcds, q = n / kXcds, rem = n % kXcds;
+    const uint32_t t = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + k;
+    return make_int2(static_cast<int>(t % gridDim.x), static_cast<int>(t / gridDim.x));
+}
+
 // FP32 pass over one frame: one 256-lane workgroup per tile (REJ: the rejection variant
 // of Eq. (11)).  Its unrolled rows with FP32 sums per row pair need ~150 registers: 3 waves per
 // SIMD (the pass runs as fast at 2, 3 or 4 waves per SIMD).
 template <int R, bool REJ, bool STR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QC_F32_WAVES_PER_EU)))
 void fit_tile_f32(FitDesc d, RefitList list) {
-    fit_tile_body<float, R, REJ, STR>(d, blockIdx.x, blockIdx.y, 0u, list);
+    const int2 t = xcd_tile();
+    fit_tile_body<float, R, REJ, STR>(d, t.x, t.y, 0u, list);
 }
 
 // FP64 pass over every pixel of one frame: tiles 16 pixels wide, QC_F64_BLOCK lanes.
@@ -38,7 +53,8 @@ void fit_tile_f32(FitDesc d, RefitList list) {
 template <int R, bool REJ, bool STR>
 __global__ __launch_bounds__(QC_F64_BLOCK) __attribute__((amdgpu_waves_per_eu(QC_F64_TILE_WAVES)))
 void fit_tile_f64(FitDesc d, RefitList list) {
-    fit_tile_body<double, R, REJ, STR>(d, blockIdx.x, blockIdx.y, 0u, list);
+    const int2 t = xcd_tile();
+    fit_tile_body<double, R, REJ, STR>(d, t.x, t.y, 0u, list);
 }
 
 // FP64 pass over the listed pixels of one frame; one wave per workgroup, persistent
