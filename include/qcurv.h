@@ -181,7 +181,7 @@ qc_status qc_fit_batch(qc_context* ctx, const qc_batch_item* items, int32_t n, v
  * request, also in FP64 throughout, `reps` times each after one warm-up call, timed with
  * HIP events on `stream`, writing into `out` (whose contents are then undefined).  It
  * records the fastest tile width and the schedule of MIXED requests for that
- * configuration: QC_PREC_MIXED (the FP32 pass plus the FP64 recomputation of the pixels
+ * configuration (a candidate displaces width 16 and MIXED only when more than 1 % faster): QC_PREC_MIXED (the FP32 pass plus the FP64 recomputation of the pixels
  * it lists) or QC_PREC_FP64 (every pixel in FP64: more accurate, and faster where the FP32
  * pass would list many pixels).  Later requests of that configuration with tile_width 0
  * use the recorded width, and MIXED ones the recorded schedule (their flags then mark

@@ -605,14 +605,19 @@ qc_status qc_tune(qc_context* ctx, const qc_frame* frame, const qc_params* param
             r = hip_fail(ctx, e);
         return r;
     };
+    // A candidate replaces the choice so far only if it is faster by more than kMargin:
+    // the default (width 16, MIXED) stays unless another is measurably faster, so that
+    // timing noise between near-equal shapes does not decide.
+    constexpr float kMargin = 0.01f;
     TuneEntry best;
     float best_ms = 0.f;
-    for (int tw = 8; tw <= 64 && st == QC_OK; tw *= 2) {
+    for (int tw : {16, 8, 32, 64}) {
+        if (st != QC_OK) break;
         qc_params p = *params;
         p.tile_width = tw;   // an explicit width: the fit runs at the requested precision
         float ms = 0.f;
         st = time_fits(p, &ms);
-        if (st == QC_OK && (tw == 8 || ms < best_ms)) {
+        if (st == QC_OK && (tw == 16 || ms < best_ms * (1.f - kMargin))) {
             best.tile_width = tw;
             best_ms = ms;
         }
@@ -624,7 +629,7 @@ qc_status qc_tune(qc_context* ctx, const qc_frame* frame, const qc_params* param
         p.precision = QC_PREC_FP64;
         float ms = 0.f;
         st = time_fits(p, &ms);
-        if (st == QC_OK && ms < best_ms) best.schedule = QC_PREC_FP64;
+        if (st == QC_OK && ms < best_ms * (1.f - kMargin)) best.schedule = QC_PREC_FP64;
     }
     ctx->timing = timing;
     (void)hipEventDestroy(a);
