@@ -438,6 +438,55 @@ def measure_batched(ctx, reps: int = 5, tune_reps: int = 3) -> dict:
     return res
 
 
+def measure_served_headline(ctx, frames, cam, n: int = 400) -> dict:
+    """The headline workload through the serving loop: n host frames (the 8 headline frames
+    cycled, 640x480 u16, r = 7, T = 5) submitted at once, batched by the server (up to 32
+    per batch, two in flight), against n plain per-frame fits of the same device-resident
+    frames one after another on one stream.  The served rate includes the uploads from
+    pinned host staging; the plain rate does not."""
+    import torch
+    from paper_1707_00385_amd.api import Server, make_outputs, make_params, upload_depth
+    K = (cam.fx, cam.fy, cam.cx, cam.cy)
+    p = make_params(radius=RADIUS, iterations=ITERS, k=K_ROBUST, normal_radius=NRAD)
+    valid = [int(np.sum(f > 0)) for f in frames]
+
+    def served() -> float:
+        srv = Server(ctx, memory_budget=2 << 30, max_batch=32, max_in_flight=2)
+        try:
+            t0 = time.perf_counter()
+            submitted = done = 0
+            while done < n:
+                while submitted < n:
+                    if srv.submit(frames[submitted % N_FRAMES], "u16", K, p, tag=submitted) is None:
+                        break
+                    submitted += 1
+                for c in srv.poll(64, wait_us=500):
+                    assert c.status == 0
+                    srv.release(c.ticket)
+                    done += 1
+            return time.perf_counter() - t0
+        finally:
+            srv.close()
+
+    served()   # warm-up (graphs, staging)
+    t_served = served()
+    dev = [upload_depth(f, "u16") for f in frames]
+    out = make_outputs(cam.height, cam.width, dev[0].device, flags=False)
+    for i in range(20):
+        ctx.fit(dev[i % N_FRAMES], K, params=p, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n):
+        ctx.fit(dev[i % N_FRAMES], K, params=p, out=out)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    px = sum(valid[i % N_FRAMES] for i in range(n))
+    return {"frames": n, "served": {"ms_per_frame": round(1e3 * t_served / n, 4),
+                                     "valid_pixels_per_s": round(px / t_served, 1)},
+            "plain": {"ms_per_frame": round(1e3 * t_plain / n, 4), "valid_pixels_per_s": round(px / t_plain, 1)},
+            "ratio": round(t_plain / t_served, 3)}
+
+
 def measure_precision_modes(ctx, dev, K, steps: int = 100) -> dict:
     """The headline frames in the other two precision modes: FP64 throughout (every pixel
     fitted in double precision) and FP32 only (no recomputation, so unreliable pixels keep
@@ -818,6 +867,8 @@ def main() -> int:
     if not args.no_batched and args.precision != "fp64":
         result["batched_form"] = measure_batched(ctx)
     served_samples = []
+    if not args.no_served and args.precision == "mixed":
+        result["served_headline"] = measure_served_headline(ctx, frames, cam)
     if not args.no_served and args.precision != "fp64":
         # the serving configuration: tile widths and schedules tuned for every sensor kind
         # and radius of the trace (shared by the served and the plain path), a 60 s realtime
