@@ -454,22 +454,22 @@ def measure_served_headline(ctx, frames, cam, n: int = 400) -> dict:
         srv = Server(ctx, memory_budget=2 << 30, max_batch=32, max_in_flight=2)
         try:
             t0 = time.perf_counter()
-            submitted = done = 0
+            submitted = done = failed = 0
             while done < n:
                 while submitted < n:
                     if srv.submit(frames[submitted % N_FRAMES], "u16", K, p, tag=submitted) is None:
                         break
                     submitted += 1
                 for c in srv.poll(64, wait_us=500):
-                    assert c.status == 0
+                    failed += c.status != 0
                     srv.release(c.ticket)
                     done += 1
-            return time.perf_counter() - t0
+            return time.perf_counter() - t0, failed
         finally:
             srv.close()
 
     served()   # warm-up (graphs, staging)
-    t_served = served()
+    t_served, failed = served()
     dev = [upload_depth(f, "u16") for f in frames]
     out = make_outputs(cam.height, cam.width, dev[0].device, flags=False)
     for i in range(20):
@@ -481,8 +481,8 @@ def measure_served_headline(ctx, frames, cam, n: int = 400) -> dict:
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     px = sum(valid[i % N_FRAMES] for i in range(n))
-    return {"frames": n, "served": {"ms_per_frame": round(1e3 * t_served / n, 4),
-                                     "valid_pixels_per_s": round(px / t_served, 1)},
+    return {"frames": n, "failed": failed, "served": {"ms_per_frame": round(1e3 * t_served / n, 4),
+                                                      "valid_pixels_per_s": round(px / t_served, 1)},
             "plain": {"ms_per_frame": round(1e3 * t_plain / n, 4), "valid_pixels_per_s": round(px / t_plain, 1)},
             "ratio": round(t_plain / t_served, 3)}
 
