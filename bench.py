@@ -362,7 +362,7 @@ def measure_served(ctx, duration_s: float = 4.0, fps: float = 240.0, sensors: in
     return res
 
 
-def measure_batched(ctx, reps: int = 5, tune_reps: int = 3) -> dict:
+def measure_batched(ctx, reps: int = 5, tune_reps: int = 3, tune: bool = True) -> dict:
     """The batched form: 64 frames in equal thirds of 512x424 ToF-like, 640x480 and
     1280x720 depth, window radius from {3, 5, 7, 11}, iterations from {3, 5} (seeded), fitted
     by one qc_fit_batch call (persistent launches replayed from a graph) and, for
@@ -410,6 +410,10 @@ def measure_batched(ctx, reps: int = 5, tune_reps: int = 3) -> dict:
 
     res = {"frames": len(jobs), "pixels_per_batch": pixels}
     res.update(timed(ctx))
+    res["mix"] = ("64 frames: 1/3 each 512x424 ToF (sigma=1e-3 Z), 640x480 and 1280x720 "
+                  "Kinect-like u16; r in {3,5,7,11}, T in {3,5}, seeded")
+    if not tune:
+        return res
     tuned_ctx = Context(0)
     try:
         t0 = time.perf_counter()
@@ -433,8 +437,6 @@ def measure_batched(ctx, reps: int = 5, tune_reps: int = 3) -> dict:
     res["tuned"] = dict(tuned, tuning_seconds=round(tune_s, 2), table=table,
                         speedup_over_untuned_batch=round(res["batched"]["ms_per_batch"] /
                                                          tuned["batched"]["ms_per_batch"], 3))
-    res["mix"] = ("64 frames: 1/3 each 512x424 ToF (sigma=1e-3 Z), 640x480 and 1280x720 "
-                  "Kinect-like u16; r in {3,5,7,11}, T in {3,5}, seeded")
     return res
 
 
@@ -551,7 +553,7 @@ PAPER_GRID_MS = {(640, 480): (10.2, 16.1, 19.3), (512, 424): (6.7, 12.2, 13.2),
 PAPER_PATCHES = ((4, 1, "9x9"), (10, 1, "21x21"), (18, 3, "37x37 every 3rd pixel (13x13 samples)"))
 
 
-def measure_paper_grid(ctx, steps: int = 50) -> list:
+def measure_paper_grid(ctx, steps: int = 50, tune: bool = True) -> list:
     """The paper's timing grid on this GPU: three image sizes x three patches (T = 5), one
     seeded cluttered u16 frame per size, per-frame launches: MIXED with the default tile
     width, FP64 throughout, and MIXED after qc_tune (on a context of its own) has recorded
@@ -585,14 +587,15 @@ def measure_paper_grid(ctx, steps: int = 50) -> list:
                 refit = ctx.last_refit_count() / (w * h)
                 ms64 = timed(ctx, make_params(radius=r, iterations=ITERS, k=K_ROBUST, stride=stride,
                                               precision="fp64"))
-                tw, sched = tuned_ctx.tune(t, K, p, reps=5, with_schedule=True)
-                ms_tuned = timed(tuned_ctx, p)
-                rows.append({"image": f"{w}x{h}", "patch": label, "radius": r, "stride": stride,
-                             "ms_per_frame": round(ms, 4), "pixels_per_s": round(w * h / ms * 1e3, 1),
-                             "refit_fraction": round(refit, 4), "fp64_mode_ms_per_frame": round(ms64, 4),
-                             "tuned": {"tile_width": tw, "schedule": {0: "mixed", 2: "fp64"}.get(sched, str(sched)),
-                                       "ms_per_frame": round(ms_tuned, 4)},
-                             "paper_k40c_ms": PAPER_GRID_MS[(w, h)][j]})
+                row = {"image": f"{w}x{h}", "patch": label, "radius": r, "stride": stride,
+                       "ms_per_frame": round(ms, 4), "pixels_per_s": round(w * h / ms * 1e3, 1),
+                       "refit_fraction": round(refit, 4), "fp64_mode_ms_per_frame": round(ms64, 4),
+                       "paper_k40c_ms": PAPER_GRID_MS[(w, h)][j]}
+                if tune:
+                    tw, sched = tuned_ctx.tune(t, K, p, reps=5, with_schedule=True)
+                    row["tuned"] = {"tile_width": tw, "schedule": {0: "mixed", 2: "fp64"}.get(sched, str(sched)),
+                                    "ms_per_frame": round(timed(tuned_ctx, p), 4)}
+                rows.append(row)
     finally:
         tuned_ctx.close()
     return rows
@@ -731,6 +734,9 @@ def main() -> int:
     ap.add_argument("--no-paper-grid", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-precision-modes", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip qc_tune in the timing grid, the batched form and the served trace "
+                         "(their untuned figures only; for profiling runs)")
     ap.add_argument("--trace-seconds", type=float, default=0.0,
                     help="length of every served trace (default: 60 s at 240 frames/s, 10 s at "
                          "1000 frames/s, 3 s at the lower rates)")
@@ -861,11 +867,11 @@ def main() -> int:
     if not args.no_reject:
         result["rejection_variant"] = measure_rejection(ctx, dev, K, args.precision)
     if not args.no_paper_grid and args.precision == "mixed":
-        result["paper_timing_grid"] = measure_paper_grid(ctx)
+        result["paper_timing_grid"] = measure_paper_grid(ctx, tune=not args.no_tune)
     if not args.no_accuracy and args.precision == "mixed":
         result["accuracy"] = measure_accuracy(ctx)
     if not args.no_batched and args.precision != "fp64":
-        result["batched_form"] = measure_batched(ctx)
+        result["batched_form"] = measure_batched(ctx, tune=not args.no_tune)
     served_samples = []
     if not args.no_served and args.precision == "mixed":
         result["served_headline"] = measure_served_headline(ctx, frames, cam)
@@ -875,11 +881,12 @@ def main() -> int:
         # trace at 240 frames/s (every 50th served frame sampled for the oracle check of
         # the CPU-baseline leg), then the same trace queued at once (saturated)
         t_tune = time.perf_counter()
-        tuned = tune_for_sensors(ctx)
+        tuned = tune_for_sensors(ctx) if not args.no_tune else []
         t_tune = time.perf_counter() - t_tune
         sv = measure_served(ctx, duration_s=args.trace_seconds or 60.0, sample_every=50,
                             samples=served_samples)
-        sv["tuned"] = {"seconds": round(t_tune, 2), "table": tuned}
+        if tuned:
+            sv["tuned"] = {"seconds": round(t_tune, 2), "table": tuned}
         result["served_form"] = sv
         result["served_vs_plain"] = {
             "saturated_throughput_ratio": round(sv["served_saturated"]["pixels_per_s"] /
