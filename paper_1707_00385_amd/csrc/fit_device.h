@@ -71,8 +71,41 @@ template <> __device__ __forceinline__ double rsqrtT(double x) {
     return x < INFINITY ? r : 0.0;
 }
 
+// 1/x for finite x > 0: hardware estimate y refined by y (1 + e + e^2), e = 1 - x y
+// (third-order convergence, so the estimate's error is cubed).
+__device__ __forceinline__ double rcp_pos(double x) {
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, __builtin_fma(e, e, e), y);
+}
+
 template <typename T> __device__ __forceinline__ T sqrtT(T x) { return sqrt(x); }
 template <typename T> __device__ __forceinline__ T sinT(T x) { return sin(x); }
+
+// Coefficients 1/n! (n! is exact in double up to 20!, so each is correctly rounded).
+__host__ __device__ constexpr double inv_factorial(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return 1.0 / f;
+}
+
+// The two factors of the exact rotation Exp([w]x) with th^2 = |w|^2 < 1:
+// st = sin(th)/th = sum_n (-th^2)^n / (2n+1)!, c1 = (1 - cos th)/th^2 = sum_n (-th^2)^n / (2n+2)!,
+// summed by Horner's rule up to the first omitted term below the type's rounding (for
+// th^2 <= 1 that term is at most 1/(2N+1)! resp. 1/(2N+2)!: N = 5 in FP32, 9 in FP64).
+template <typename T>
+__device__ __forceinline__ void rotation_series(T th2, T& st, T& c1) {
+    constexpr int N = sizeof(T) == 4 ? 5 : 9;
+    const T nx = -th2;
+    T s = T(inv_factorial(2 * N - 1)), c = T(inv_factorial(2 * N));
+#pragma unroll
+    for (int n = N - 2; n >= 0; --n) {
+        s = fmaT(s, nx, T(inv_factorial(2 * n + 1)));
+        c = fmaT(c, nx, T(inv_factorial(2 * n + 2)));
+    }
+    st = s;
+    c1 = c;
+}
 
 // ---------------------------------------------------------------------------- depth
 __device__ __forceinline__ float load_sample(const FitDesc& d, int x, int y) {
@@ -492,27 +525,33 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         gv[0] = G0; gv[1] = G1; gv[2] = -G2; gv[3] = Acc(0.5) * G3; gv[4] = G4; gv[5] = Acc(0.5) * G5;
 
         // Jacobi equilibration, then LDL^T with pivots dp[j] of the unit-diagonal matrix.
+        // Column j keeps U[i][j] = L[i][j] dp[j] (the sum before the division by the pivot)
+        // beside L[i][j], so that every elimination step is one fused multiply-add.
         Acc dsc[6];
         bool singular = false;
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            singular |= !(Hm[i][i] > Acc(0));
-            dsc[i] = Hm[i][i] > Acc(0) ? rsqrtT(Hm[i][i]) : Acc(0);
+            const Acc hii = Hm[i][i];
+            singular |= !(hii > Acc(0));
+            const Acc r = rsqrtT(hii > Acc(0) ? hii : Acc(1));
+            dsc[i] = hii > Acc(0) ? r : Acc(0);
         }
-        Acc L[6][6], dp[6], idp[6];
+        Acc L[6][6], U[6][6], dp[6], idp[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
             Acc dj = Acc(1);   // equilibrated diagonal
 #pragma unroll
-            for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k] * dp[k];
+            for (int k = 0; k < j; ++k) dj = fmaT(-L[j][k], U[j][k], dj);
             dp[j] = dj;
-            const Acc idj = dj > Acc(0) ? Acc(1) / dj : Acc(0);
+            const Acc rj = rcp_pos(dj > Acc(0) ? dj : Acc(1));
+            const Acc idj = dj > Acc(0) ? rj : Acc(0);
             idp[j] = idj;
 #pragma unroll
             for (int i = j + 1; i < 6; ++i) {
                 Acc sij = dsc[i] * dsc[j] * Hm[j][i];
 #pragma unroll
-                for (int k = 0; k < j; ++k) sij -= L[i][k] * L[j][k] * dp[k];
+                for (int k = 0; k < j; ++k) sij = fmaT(-L[i][k], U[j][k], sij);
+                U[i][j] = sij;
                 L[i][j] = sij * idj;
             }
         }
@@ -531,14 +570,14 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         for (int i = 0; i < 6; ++i) {
             Acc sy = dsc[i] * gv[i];
 #pragma unroll
-            for (int k = 0; k < i; ++k) sy -= L[i][k] * y[k];
+            for (int k = 0; k < i; ++k) sy = fmaT(-L[i][k], y[k], sy);
             y[i] = sy;
         }
 #pragma unroll
         for (int i = 5; i >= 0; --i) {
             Acc sb = y[i] * idp[i];
 #pragma unroll
-            for (int k = i + 1; k < 6; ++k) sb -= L[k][i] * b[k];
+            for (int k = i + 1; k < 6; ++k) sb = fmaT(-L[k][i], b[k], sb);
             b[i] = sb;
         }
 #pragma unroll
@@ -553,8 +592,10 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         {
             const Real w0 = Real(-b[0]), w1 = Real(-b[1]);
             const Real th2 = w0 * w0 + w1 * w1;
-            Real st = Real(1), c1 = Real(0.5);
-            if (th2 > Real(0)) {
+            Real st, c1;
+            if (th2 < Real(1)) {
+                rotation_series(th2, st, c1);
+            } else {
                 const Real th = sqrtT(th2);
                 const Real ith = Real(1) / th;
                 st = sinT(th) * ith;                        // sin(th)/th
