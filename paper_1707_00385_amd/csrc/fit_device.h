@@ -54,9 +54,9 @@ constexpr float kRejectMargin = 2e-5f;
 #endif
 
 // ---------------------------------------------------------------------------- scalars
-template <typename T> __device__ __forceinline__ T fmaT(T a, T b, T c);
-template <> __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <> __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename T> __host__ __device__ __forceinline__ T fmaT(T a, T b, T c);
+template <> __host__ __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __host__ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // 1/sqrt(x) with 1/sqrt(+inf) = 0 (the weight of a missing neighbour).
 template <typename T> __device__ __forceinline__ T rsqrtT(T x);
@@ -94,7 +94,7 @@ __host__ __device__ constexpr double inv_factorial(int n) {
 // summed by Horner's rule up to the first omitted term below the type's rounding (for
 // th^2 <= 1 that term is at most 1/(2N+1)! resp. 1/(2N+2)!: N = 5 in FP32, 9 in FP64).
 template <typename T>
-__device__ __forceinline__ void rotation_series(T th2, T& st, T& c1) {
+__host__ __device__ __forceinline__ void rotation_series(T th2, T& st, T& c1) {
     constexpr int N = sizeof(T) == 4 ? 5 : 9;
     const T nx = -th2;
     T s = T(inv_factorial(2 * N - 1)), c = T(inv_factorial(2 * N));

@@ -18,6 +18,25 @@ def test_range_allocator_first_fit_and_coalescing(tmp_path):
     assert out.strip() == "OK"
 
 
+def test_rotation_series_of_the_update_matches_its_trigonometric_definition(tmp_path):
+    """The kernels' update builds the exact rotation Exp([w]x) from sin(th)/th and
+    (1 - cos th)/th^2, summed as series in th^2 when th^2 < 1.  The header's own series
+    (compiled for the host) is held to the trigonometric definitions in long double, to
+    2 units in the last place, in FP32 and FP64."""
+    import shutil
+    import pytest
+    hipcc = shutil.which("hipcc") or ("/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else None)
+    if hipcc is None:
+        pytest.skip("hipcc not available")
+    exe = tmp_path / "test_rotation_series"
+    subprocess.run([hipcc, "-x", "hip", "--cuda-host-only", "-O2", "-std=c++17",
+                    "-I", os.path.join(ROOT, "paper_1707_00385_amd", "csrc"), "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "cpp", "test_rotation_series.cpp"), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0 and out.stdout.strip().endswith("OK"), out.stdout
+
+
 def test_algorithmic_flop_count_matches_brute_force():
     """bench.py prices the headline kernel by T (97 |S| + 250) + 14 |S_n| + 40 flops per
     valid pixel, with |S|, |S_n| counted by summed-area tables; here the window counts
