@@ -18,6 +18,7 @@
 #include "api_internal.h"
 #include "fit_internal.h"
 #include "qcurv.h"
+#include "tune_table.h"
 
 namespace {
 
@@ -43,15 +44,8 @@ struct BatchSlot {
     bool in_flight = false;
 };
 
-// width, height, radius, iterations, stride, reject
-using TuneKey = std::tuple<int, int, int, int, int, int>;
-// What qc_tune recorded for a key: the FP32 pass's tile width, and the schedule of a MIXED
-// request: QC_PREC_MIXED (the FP32 pass plus the FP64 recomputation of listed pixels) or
-// QC_PREC_FP64 (every pixel in FP64, where that measured faster).
-struct TuneEntry {
-    int tile_width = 16;
-    int schedule = QC_PREC_MIXED;
-};
+using qc::TuneEntry;
+using qc::TuneKey;
 
 TuneKey tune_key(const qc_frame* f, const qc_params* p) {
     return TuneKey{f->width, f->height, p->radius, p->iterations, p->stride, p->reject};
@@ -645,11 +639,9 @@ qc_status qc_tune_save(qc_context* ctx, const char* path) {
     if (!ctx || !path) return QC_ERR_INVALID_ARG;
     FILE* f = std::fopen(path, "w");
     if (!f) return QC_ERR_INVALID_ARG;
-    for (const auto& kv : ctx->tuned)
-        std::fprintf(f, "%d %d %d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
-                     std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first),
-                     std::get<5>(kv.first), kv.second.tile_width, kv.second.schedule);
-    return std::fclose(f) == 0 ? QC_OK : QC_ERR_INVALID_ARG;
+    bool ok = true;
+    for (const auto& kv : ctx->tuned) ok = qc::format_tune_line(f, kv.first, kv.second) > 0 && ok;
+    return std::fclose(f) == 0 && ok ? QC_OK : QC_ERR_INVALID_ARG;
 }
 
 qc_status qc_tune_load(qc_context* ctx, const char* path) {
@@ -660,28 +652,14 @@ qc_status qc_tune_load(qc_context* ctx, const char* path) {
     qc_status st = QC_OK;
     std::map<TuneKey, TuneEntry> got;
     while (std::fgets(line, sizeof line, f)) {
-        int w, h, r, t, stride = 1, reject = 0, tw, sched = QC_PREC_MIXED;
-        char extra;
-        const int n = std::sscanf(line, "%d %d %d %d %d %d %d %d %c", &w, &h, &r, &t, &stride, &reject, &tw,
-                                  &sched, &extra);
-        if (n == EOF) continue;   // blank line
-        if (n == 5) {             // "width height radius iterations tile_width"
-            tw = stride;
-            stride = 1;
-        } else if (n != 8) {
-            st = QC_ERR_INVALID_ARG;
-            break;
-        }
-        if (w < 1 || h < 1 || r < 1 || r > QC_MAX_RADIUS || t < 0 || stride < 1 || stride > r ||
-            (reject != 0 && reject != 1) || !qc::valid_tile_width(tw) ||
-            (sched != QC_PREC_MIXED && sched != QC_PREC_FP64)) {
-            st = QC_ERR_INVALID_ARG;
-            break;
-        }
+        TuneKey k;
         TuneEntry e;
-        e.tile_width = tw;
-        e.schedule = sched;
-        got[TuneKey{w, h, r, t, stride, reject}] = e;
+        const int r = qc::parse_tune_line(line, &k, &e, qc::valid_tile_width);
+        if (r < 0) {
+            st = QC_ERR_INVALID_ARG;
+            break;
+        }
+        if (r > 0) got[k] = e;
     }
     std::fclose(f);
     if (st != QC_OK) return st;   // a malformed file changes nothing

@@ -18,6 +18,19 @@ def test_range_allocator_first_fit_and_coalescing(tmp_path):
     assert out.strip() == "OK"
 
 
+def test_tune_table_records_parse_and_round_trip(tmp_path):
+    """qc_tune_save / qc_tune_load go through tune_table.h: both record forms, blank lines,
+    eighteen kinds of malformed line (field counts, values qc_fit would refuse, numbers out
+    of int range, junk after a number), and random records written and read back."""
+    exe = tmp_path / "test_tune_table"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-Wall",
+                    "-I", os.path.join(ROOT, "paper_1707_00385_amd", "csrc"), "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "cpp", "test_tune_table.cpp"), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0 and out.stdout.strip() == "OK", out.stdout
+
+
 def test_rotation_series_of_the_update_matches_its_trigonometric_definition(tmp_path):
     """The kernels' update builds the exact rotation Exp([w]x) from sin(th)/th and
     (1 - cos th)/th^2, summed as series in th^2 when th^2 < 1.  The header's own series
