@@ -85,10 +85,11 @@ typedef struct {
     float depth_scale;       /* metres per unit of U16 depth; ignored for F16/F32 */
     int32_t precision;       /* qc_precision */
     float cond_max;          /* MIXED: refit if the equilibrated pivot ratio exceeds this */
-    float step_max;          /* MIXED: refit if the last update exceeds this, measured in
-                                window units: radians, t_z / h_w and h_w * (A, B, C), with
-                                h_w = r Z / fx the window half-extent at the pixel; for
-                                r > 7 (any stride) the bound applied is step_max * (7/r)^2 */
+    float step_max;          /* MIXED: refit if the last update exceeds this, or the update
+                                before it exceeds 1.5 times this, measured in window units:
+                                radians, t_z / h_w and h_w * (A, B, C), with h_w = r Z / fx
+                                the window half-extent at the pixel; for r > 7 (any stride)
+                                the bound applied is step_max * (7/r)^2 */
     int32_t tile_width;      /* FP32 pass tile: 8, 16, 32 or 64 pixels wide (256 pixels);
                                 0 = the width (and, for MIXED, the schedule) qc_tune
                                 recorded for this configuration, else 16 and MIXED.  Results

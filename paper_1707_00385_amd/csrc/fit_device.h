@@ -40,6 +40,13 @@ constexpr int kTileW = 16;
 // Relative distance from the rejection bound R within which an FP32 decision e^2 < R is
 // not trusted (about 10x the FP32 error of e^2 for residuals at the noise level).
 constexpr float kRejectMargin = 2e-5f;
+// Further reasons to recompute an FP32 fit in FP64 (measured against the oracle): a normal
+// regression with det M <= kNormalDetMin (tr M)^2 starts the fit from an initial normal that
+// FP32 and FP64 place differently enough to end apart, and an update before the last one
+// larger than kPrevStepFactor times the last-update bound means the fit was still moving
+// far one step before the end, where an FP32 step lands differently from the FP64 one.
+constexpr float kNormalDetMin = 1e-2f;
+constexpr float kPrevStepFactor = 1.5f;
 
 // Compile-time tuning (measured defaults): waves per SIMD of the FP32 pass and of the
 // FP64 recomputation, neighbours per unrolled step of the FP64 window loops.
@@ -372,7 +379,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         if (fp32) out.flags = kFlagIll;   // let FP64 decide
         return out;
     }
-    if (fp32 && !(det > Real(1e-3) * tr * tr)) ill = true;
+    if (fp32 && !(det > Real(kNormalDetMin) * tr * tr)) ill = true;
     const Real ia = (M11 * v0 - M01 * v1) / det;
     const Real ib = (M00 * v1 - M01 * v0) / det;
     const Real nsc = Real(1) / sqrtT(Real(1) + ia * ia + ib * ib);
@@ -395,7 +402,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         R[2][0] = -wy;                    R[2][1] = wx;                     R[2][2] = n0z;
     }
     Real tz = 0, A = 0, B = 0, C = 0;     // patch coefficients in units of h
-    Acc last_step = 0;
+    Acc last_step = 0, prev_step = 0;     // sizes of the last two updates
     bool cond_ok = true;                  // pivot ratio within cond_max at every iteration
     bool near = false;                    // an FP32 rejection decision was too close to call
     // window half-extent r Z_c / fx in units of h
@@ -584,6 +591,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         for (int i = 0; i < 6; ++i) b[i] *= dsc[i];
         // Size of the update in window units (angles in radians, t_z in window
         // half-extents, curvatures times the half-extent): how far from converged.
+        prev_step = last_step;
         last_step = fmax(fmax(fabs(b[0]), fabs(b[1])),
                          fmax(fabs(b[2]) * ihwin, hwin * fmax(fmax(fabs(b[3]), fabs(b[4])), fabs(b[5]))));
 
@@ -693,7 +701,8 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
     out.n[1] = R[2][1];
     out.n[2] = R[2][2];
     out.flags = kFlagValid | (fp32 ? 0 : kFlagFp64);
-    if (fp32 && (ill || near || !cond_ok || !(last_step <= Acc(d.step_max))))
+    if (fp32 && (ill || near || !cond_ok || !(last_step <= Acc(d.step_max)) ||
+                 !(prev_step <= Acc(kPrevStepFactor) * Acc(d.step_max))))
         out.flags |= kFlagIll;
     return out;
 }
