@@ -81,7 +81,9 @@ typedef struct {
                                 of e^2 over the window at the current parameters
                                 (Section 3.2.3; nothing rejected when that mean is 0).
                                 MIXED also recomputes in FP64 every pixel with an FP32
-                                decision within a relative 2e-5 of R. */
+                                decision too close to R to be sure of (within a relative
+                                1e-4, or closer than FP32 resolves e^2 in that window) or
+                                an update after the first iteration beyond 5 step_max. */
     float depth_scale;       /* metres per unit of U16 depth; ignored for F16/F32 */
     int32_t precision;       /* qc_precision */
     float cond_max;          /* MIXED: refit if the equilibrated pivot ratio exceeds this */

@@ -38,8 +38,14 @@ constexpr int kMaxRadius = 18;
 constexpr uint8_t kFlagValid = 1, kFlagFp64 = 2, kFlagIll = 4;
 constexpr int kTileW = 16;
 // Relative distance from the rejection bound R within which an FP32 decision e^2 < R is
-// not trusted (about 10x the FP32 error of e^2 for residuals at the noise level).
-constexpr float kRejectMargin = 2e-5f;
+// not trusted (measured: decisions 1.6e-5 from R have gone the other way in FP64).
+constexpr float kRejectMargin = 1e-4f;
+// ... and within kRejectAbs * sqrt(R) * m of it, m the window's largest |terms| of the local
+// depth coordinate (in units of h, doubled as in the fit's loop): FP32 rounds e to about
+// 2^-24 m, which sets the error of e^2 near the bound and of the mean that sets R; it
+// exceeds the relative margin where the residuals are at the rounding level of the input
+// (noiseless float depth) or the surface is seen edge-on (large, cancelling terms).
+constexpr float kRejectAbs = 1e-6f;
 // Further reasons to recompute an FP32 fit in FP64 (measured against the oracle): a normal
 // regression with det M <= kNormalDetMin (tr M)^2 starts the fit from an initial normal that
 // FP32 and FP64 place differently enough to end apart, and an update before the last one
@@ -47,6 +53,10 @@ constexpr float kRejectMargin = 2e-5f;
 // far one step before the end, where an FP32 step lands differently from the FP64 one.
 constexpr float kNormalDetMin = 1e-2f;
 constexpr float kPrevStepFactor = 1.5f;
+// With rejection the point set changes between iterations, and a fit that still moves far
+// after its first iteration (any later update beyond kRejectSettleFactor times the
+// last-update bound) can follow a different path in FP32 than in FP64 and end far apart.
+constexpr float kRejectSettleFactor = 5.0f;
 
 // Compile-time tuning (measured defaults): waves per SIMD of the FP32 pass and of the
 // FP64 recomputation, neighbours per unrolled step of the FP64 window loops.
@@ -403,6 +413,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
     }
     Real tz = 0, A = 0, B = 0, C = 0;     // patch coefficients in units of h
     Acc last_step = 0, prev_step = 0;     // sizes of the last two updates
+    Acc later_step = 0;                   // largest update after the first (rejection)
     bool cond_ok = true;                  // pivot ratio within cond_max at every iteration
     bool near = false;                    // an FP32 rejection decision was too close to call
     // window half-extent r Z_c / fx in units of h
@@ -428,6 +439,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         // Rejection (Eq. (11) with R = 2 MSE, Section 3.2.3): R from the unweighted mean
         // of e^2 over the valid neighbours at the current parameters; none when it is 0.
         Real thresh = Real(INFINITY);
+        Real zmag = 0;   // FP32: largest |terms| of the doubled local depth coordinate
         if constexpr (REJ) {
             Acc se = 0;
             for_window<RC, sizeof(Real) == 8 ? QC_F64_UNROLL : 0>(src, radius, grp, [&](float2 t, int du, int dv) {
@@ -435,11 +447,13 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
                 const Real fdu = Real(du), fdv = Real(dv);
                 const Real sx = fmaT(fmaT(Rp[0][0], fdu, Rp[0][1] * fdv), D, Rp[0][2] * dD);
                 const Real sy = fmaT(fmaT(Rp[1][0], fdu, Rp[1][1] * fdv), D, Rp[1][2] * dD);
-                const Real sz2 = fmaT(fmaT(Rp[2][0], fdu, Rp[2][1] * fdv), D, Rp[2][2] * dD);
+                const Real a2 = fmaT(Rp[2][0], fdu, Rp[2][1] * fdv), b2 = Rp[2][2] * dD;
+                const Real sz2 = fmaT(a2, D, b2);
                 const Real qz = fmaT(Real(0.5), sz2, tz);
                 const Real ap = fmaT(Ah, sx, Bh * sy), cp = fmaT(Bh, sx, Ch * sy);
                 const Real e = fmaT(ap, sx, fmaT(cp, sy, -qz));
                 se += present(t) ? Acc(e * e) : Acc(0);
+                if constexpr (sizeof(Real) == 4) zmag = fmax(zmag, present(t) ? fabs(a2 * D) + fabs(b2) : Real(0));
             });
             se = grp.sum(se);
             const Acc mse = se / Acc(nfit);
@@ -509,7 +523,9 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
                 }
             }
         });
-        if constexpr (REJ && sizeof(Real) == 4) near |= thresh < Real(INFINITY) && gap <= Real(kRejectMargin) * thresh;
+        if constexpr (REJ && sizeof(Real) == 4)
+            near |= thresh < Real(INFINITY) &&
+                    gap <= fmax(Real(kRejectMargin) * thresh, Real(kRejectAbs) * sqrtT(thresh) * zmag);
         if constexpr (NP > 1) {
 #pragma unroll
             for (int k = 0; k < kSums; ++k) sum[k] = grp.sum(sum[k]);
@@ -594,6 +610,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         prev_step = last_step;
         last_step = fmax(fmax(fabs(b[0]), fabs(b[1])),
                          fmax(fabs(b[2]) * ihwin, hwin * fmax(fmax(fabs(b[3]), fabs(b[4])), fabs(b[5]))));
+        if constexpr (REJ) later_step = it > 0 ? fmax(later_step, last_step) : later_step;
 
         // Update (Section 3.2.3): R <- Exp([(-b0, -b1, 0)]x) R (exact Rodrigues),
         // t_z -= b2, A -= b3, B -= b4, C -= b5.
@@ -646,6 +663,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         }
         const Real Ah = Real(0.5) * A, Bh = Real(0.5) * B, Ch = Real(0.5) * C;
         Real thresh = Real(INFINITY);
+        Real zmag = 0;   // FP32: as in the fit's loop (the coordinate here is not doubled)
         if constexpr (REJ) {
             Acc se = 0;
             for_window<RC, sizeof(Real) == 8 ? QC_F64_UNROLL : 0>(src, radius, grp, [&](float2 t, int du, int dv) {
@@ -658,6 +676,9 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
                 const Real ap = fmaT(Ah, sx, Bh * sy), cp = fmaT(Bh, sx, Ch * sy);
                 const Real e = fmaT(ap, sx, fmaT(cp, sy, -qz));
                 se += present(t) ? Acc(e * e) : Acc(0);
+                if constexpr (sizeof(Real) == 4)
+                    zmag = fmax(zmag, present(t) ? Real(2) * (fabs(Rp[2][0] * mx) + fabs(Rp[2][1] * my) + fabs(Rp[2][2] * dD))
+                                                 : Real(0));
             });
             se = grp.sum(se);
             const Acc mse = se / Acc(nfit);
@@ -684,7 +705,9 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
             sw += w;
             swe = fmaT(w * e, e, swe);
         });
-        if constexpr (REJ && sizeof(Real) == 4) near |= thresh < Real(INFINITY) && gap <= Real(kRejectMargin) * thresh;
+        if constexpr (REJ && sizeof(Real) == 4)
+            near |= thresh < Real(INFINITY) &&
+                    gap <= fmax(Real(kRejectMargin) * thresh, Real(kRejectAbs) * sqrtT(thresh) * zmag);
         sw = grp.sum(sw);
         swe = grp.sum(swe);
         out.residual = g.h * sqrtT(swe / sw);
@@ -702,7 +725,8 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
     out.n[2] = R[2][2];
     out.flags = kFlagValid | (fp32 ? 0 : kFlagFp64);
     if (fp32 && (ill || near || !cond_ok || !(last_step <= Acc(d.step_max)) ||
-                 !(prev_step <= Acc(kPrevStepFactor) * Acc(d.step_max))))
+                 !(prev_step <= Acc(kPrevStepFactor) * Acc(d.step_max)) ||
+                 (REJ && !(later_step <= Acc(kRejectSettleFactor) * Acc(d.step_max)))))
         out.flags |= kFlagIll;
     return out;
 }
