@@ -85,6 +85,25 @@ def test_vga_noiseless_full_frame(ctx):
          normal_tol=1e-4, residual_tol=1e-3)
 
 
+def test_vga_noiseless_near_singular_initial_normal(ctx):
+    """A noiseless frame with a cluster of pixels whose 7x7 normal regression is nearly
+    singular (det M / (tr M)^2 = 0.002): FP32 and FP64 place the initial normal differently
+    enough to end apart, so these must be recomputed (a determinant bound of 1e-3 left five
+    of them at up to 4.6 times the tolerance)."""
+    sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=20, config_index=1, noise=False,
+                                dropout=0.0)
+    _run(ctx, "vga f32 noiseless seed 20", sc.depth_m, "f32", sc.camera, 7, 5, 1e-4, scene=sc)
+
+
+@pytest.mark.parametrize("kind", ["tof", "hd"])
+def test_sensor_frames_whose_fit_moved_late(ctx, kind):
+    """Noisy ToF and 720p frames, every pixel: each holds a pixel whose fit moved 0.2-0.6
+    window units in the iteration before the last and that FP32 ends 2-7 times the
+    tolerance away from FP64 (recomputed since the update before the last is bounded)."""
+    sc = scenes.sensor_frame(kind, seed_frame=0)
+    _run(ctx, f"{kind} u16 seed 0", sc.depth_u16(), "u16", sc.camera, 7, 5, 1e-3, scene=sc)
+
+
 # A camera whose focal lengths differ (pixels 1.2 % taller than wide): back-projection
 # divides the row offset by fy and the column offset by fx (Section 3.2, pinhole model).
 CAM_VGA_ANISO = scenes.Camera(640, 480, 525.0, 518.9, 319.5, 239.5)
@@ -170,6 +189,40 @@ def test_reject_clutter_small(ctx, fmt):
 def test_reject_vga_headline(ctx):
     sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=2, config_index=1)
     st, g, _ = _run(ctx, "reject vga u16", sc.depth_u16(), "u16", sc.camera, 7, 5, 1e-3, reject=True)
+    log("  refit fraction", st["refits"] / st["pixels"])
+
+
+def test_reject_vga_noiseless_float(ctx):
+    """Rejection on a noiseless float frame, every pixel, at the noiseless tolerance.  The
+    residuals of its flat regions are at the rounding level of the float depth, where the
+    FP32 pass cannot decide e^2 < R as FP64 does: such pixels must be left to FP64 (an
+    earlier margin, a fixed 2e-5 of R, left 3,088 of them beyond the tolerance here)."""
+    sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=29, config_index=1, noise=False, dropout=0.0)
+    # two non-unique pixels at a 0.56 m / 2.63 m depth edge, where the FP64 fit with rejection
+    # turns by tens of radians per step, end outside the oracle's envelope in FP64 on the GPU
+    st, g, _ = _run(ctx, "reject vga noiseless f32", sc.depth_m, "f32", sc.camera, 7, 5, 1e-4,
+                    reject=True, scene=sc, max_outside_at_edges=4)
+    log("  refit fraction", st["refits"] / st["pixels"])
+
+
+def test_reject_hd_edge_on_surfaces(ctx):
+    """Rejection on a noisy 1280x720 frame, every pixel: where surfaces are seen edge-on the
+    FP64 fit moves far for several iterations while its rejected set changes, and an FP32
+    fit that follows a different path must be left to FP64 (earlier criteria left three
+    pixels of this frame at 21-408 times the tolerance)."""
+    sc = scenes.sensor_frame("hd", seed_frame=0)
+    st, g, _ = _run(ctx, "reject hd u16", sc.depth_u16(), "u16", sc.camera, 7, 5, 1e-3, reject=True,
+                    scene=sc)
+    log("  refit fraction", st["refits"] / st["pixels"])
+
+
+def test_reject_vga_small_window_few_iterations(ctx):
+    """Rejection at r = 3, T = 3 on a noisy VGA frame, every pixel: one of its pixels has a
+    first-iteration decision 1.6e-5 of R from the bound in FP64, which FP32 once saw on
+    the other side (1,578 times the tolerance)."""
+    sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=23, config_index=1)
+    st, g, _ = _run(ctx, "reject vga u16 r3 T3", sc.depth_u16(), "u16", sc.camera, 3, 3, 1e-3,
+                    reject=True, scene=sc)
     log("  refit fraction", st["refits"] / st["pixels"])
 
 
