@@ -1,0 +1,95 @@
+"""Check of the MIXED recompute criteria on whole frames (GPU, run by hand, not collected by
+pytest):
+
+    python tests/criteria_study.py <set> r,T,stride[,reject] [r,T,stride[,reject] ...]
+
+For every frame of the set it fits the frame in FP32 only (the flags carry the recompute
+criteria: bit 2 = judged unreliable) and with the FP64 oracle, and counts the pixels whose
+oracle result is determined by the input (unique, as in tests.helpers.compare) and whose
+FP32 result lies beyond the tolerance although the criteria did not list them: in MIXED
+those would be wrong.  Sets (seeds of the synthetic scenes): "a" and "b" (eight noisy
+headline frames, four noiseless float VGA frames, three ToF and two 720p frames), "c"
+(held out), "c_f16" (set C with depth stored as f16 metres).  Prints one line per frame and
+a JSON summary per configuration."""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from paper_1707_00385_amd import scenes  # noqa: E402
+from tests.helpers import curv_err, oracle_fit  # noqa: E402
+
+SEEDS = {"a": (0, 20, 0, 0), "b": (8, 24, 3, 2), "c": (16, 28, 6, 4), "c_f16": (16, 28, 6, 4)}
+
+
+def frame_set(name):
+    vga, noiseless, tof, hd = SEEDS[name]
+    f16 = name.endswith("_f16")
+    frames = []
+    for i in range(8):
+        sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=vga + i, config_index=1)
+        frames.append((f"vga{i}", sc.depth_m if f16 else sc.depth_u16(), "f16" if f16 else "u16", sc.camera, 1e-3))
+    for i in range(4):
+        sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=noiseless + i, config_index=1, noise=False,
+                                    dropout=0.0)
+        frames.append((f"vga-noiseless{i}", sc.depth_m, "f16" if f16 else "f32", sc.camera, 1e-4))
+    for kind, first, n in (("tof", tof, 3), ("hd", hd, 2)):
+        for i in range(n):
+            sc = scenes.sensor_frame(kind, seed_frame=first + i)
+            frames.append((f"{kind}{i}", sc.depth_m if f16 else sc.depth_u16(), "f16" if f16 else "u16",
+                           sc.camera, 1e-3))
+    return frames
+
+
+def main(argv):
+    import torch
+    from paper_1707_00385_amd.api import Context, make_params, upload_depth
+    frames = frame_set(argv[0])
+    ctx = Context(0)
+    summary = {}
+    for cfg in argv[1:]:
+        parts = [int(x) for x in cfg.split(",")]
+        r, T, s = parts[:3]
+        rej = parts[3] if len(parts) > 3 else 0
+        key = f"r{r}_T{T}_s{s}" + ("_reject" if rej else "")
+        listed = valid = misses = 0
+        worst = 0.0
+        t0 = time.time()
+        for name, d, fmt, cam, tol in frames:
+            p = make_params(radius=r, iterations=T, stride=s, precision="fp32", reject=rej)
+            g = ctx.fit(upload_depth(d, fmt), (cam.fx, cam.fy, cam.cx, cam.cy), params=p)
+            torch.cuda.synchronize()
+            g = {k: v.cpu().numpy() for k, v in g.items()}
+            o = oracle_fit(d, fmt, cam, r, T, 1e-5, stride=s, reject=bool(rej))
+            a = oracle_fit(d, fmt, cam, r, T, 1e-5, stride=s, perturb=1, reject=bool(rej))
+            ov = o["flags"] == 1
+            unique = ov & (a["flags"] == 1) & (curv_err(a, o) <= tol / 100)
+            gv = (g["flags"] & 1) != 0
+            flagged = gv & ((g["flags"] & 4) != 0)
+            e = curv_err(g, o) / tol
+            unlisted = unique & gv & ~flagged
+            n_miss = int(np.sum(unlisted & (e > 1)))
+            w = float(np.nanmax(np.where(unlisted, e, 0)))
+            valid += int(ov.sum())
+            listed += int(flagged.sum())
+            misses += n_miss
+            worst = max(worst, w)
+            print(f"[{key}] {name}: listed {flagged.sum() / max(ov.sum(), 1) * 100:.2f} %, unlisted beyond the "
+                  f"tolerance {n_miss}, worst unlisted {w:.3f} tol ({time.time() - t0:.0f} s)", flush=True)
+        summary[key] = dict(valid=valid, listed_pct=round(listed / valid * 100, 3), unlisted_over_tol=misses,
+                            worst_unlisted_tol=round(worst, 3))
+        print(json.dumps({key: summary[key]}), flush=True)
+    ctx.close()
+    return 0 if all(v["unlisted_over_tol"] == 0 for v in summary.values()) else 1
+
+
+if __name__ == "__main__":
+    if len(sys.argv) < 3 or sys.argv[1] not in SEEDS:
+        print(__doc__)
+        sys.exit(2)
+    sys.exit(main(sys.argv[1:]))
