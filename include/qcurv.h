@@ -83,7 +83,9 @@ typedef struct {
                                 MIXED also recomputes in FP64 every pixel with an FP32
                                 decision too close to R to be sure of (within a relative
                                 1e-4, or closer than FP32 resolves e^2 in that window) or
-                                an update after the first iteration beyond 5 step_max. */
+                                an update after the first iteration beyond 5 step_max;
+                                when the residual output is requested, the decisions of
+                                its own pass count too. */
     float depth_scale;       /* metres per unit of U16 depth; ignored for F16/F32 */
     int32_t precision;       /* qc_precision */
     float cond_max;          /* MIXED: refit if the equilibrated pivot ratio exceeds this */
