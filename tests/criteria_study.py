@@ -9,8 +9,9 @@ oracle result is determined by the input (unique, as in tests.helpers.compare) a
 FP32 result lies beyond the tolerance although the criteria did not list them: in MIXED
 those would be wrong.  Sets (seeds of the synthetic scenes): "a" and "b" (eight noisy
 headline frames, four noiseless float VGA frames, three ToF and two 720p frames), "c"
-(held out), "c_f16" (set C with depth stored as f16 metres).  Prints one line per frame and
-a JSON summary per configuration."""
+(held out), "c_f16" (set C with depth stored as f16 metres), "shapes" (a sphere, a cylinder,
+a torus and a saddle alone in view, each noiseless in f32 and with 0.5 mm Gaussian noise in
+u16).  Prints one line per frame and a JSON summary per configuration."""
 import json
 import os
 import sys
@@ -24,10 +25,27 @@ sys.path.insert(0, ROOT)
 from paper_1707_00385_amd import scenes  # noqa: E402
 from tests.helpers import curv_err, oracle_fit  # noqa: E402
 
-SEEDS = {"a": (0, 20, 0, 0), "b": (8, 24, 3, 2), "c": (16, 28, 6, 4), "c_f16": (16, 28, 6, 4)}
+SEEDS = {"a": (0, 20, 0, 0), "b": (8, 24, 3, 2), "c": (16, 28, 6, 4), "c_f16": (16, 28, 6, 4), "shapes": None}
+
+
+def shape_frames():
+    cam = scenes.CAM_VGA
+    rng = np.random.default_rng([1707, 385, 99])
+    shapes = [("sphere", scenes.single_shape_scene("sphere", cam, 0.6, 0.1)),
+              ("cylinder", scenes.single_shape_scene("cylinder", cam, 0.6, 0.05, axis=(0.3, 1.0, 0.2))),
+              ("torus", scenes.torus_scene(cam, 0.6)),
+              ("saddle", scenes.saddle_scene(cam, 0.8, 0.3, scenes.random_rotation(rng)))]
+    frames = []
+    for name, sc in shapes:
+        frames.append((name + "-noiseless", sc.depth_m, "f32", sc.camera, 1e-4))
+        noisy = np.where(sc.depth_m > 0, sc.depth_m + rng.standard_normal(sc.depth_m.shape) * 5e-4, 0.0)
+        frames.append((name + "-noisy", np.rint(noisy * 1e3), "u16", sc.camera, 1e-3))
+    return frames
 
 
 def frame_set(name):
+    if name == "shapes":
+        return shape_frames()
     vga, noiseless, tof, hd = SEEDS[name]
     f16 = name.endswith("_f16")
     frames = []
