@@ -226,6 +226,13 @@ def test_reject_vga_small_window_few_iterations(ctx):
     log("  refit fraction", st["refits"] / st["pixels"])
 
 
+def test_reject_vga_half_precision_input(ctx):
+    """Rejection on a noisy VGA frame stored as f16 metres (11-bit samples), every pixel."""
+    sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=16, config_index=1)
+    st, g, _ = _run(ctx, "reject vga f16", sc.depth_m, "f16", sc.camera, 7, 5, 1e-3, reject=True, scene=sc)
+    log("  refit fraction", st["refits"] / st["pixels"])
+
+
 def test_reject_fp64_mode_tight(ctx):
     sc = scenes.cluttered_scene(scenes.Camera(96, 72, 80.0, 80.0, 47.5, 35.5), seed_frame=12,
                                 config_index=7)
