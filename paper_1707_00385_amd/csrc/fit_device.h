@@ -442,6 +442,7 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
         Real zmag = 0;   // FP32: largest |terms| of the doubled local depth coordinate
         if constexpr (REJ) {
             Acc se = 0;
+            Real rse = 0;
             for_window<RC, sizeof(Real) == 8 ? QC_F64_UNROLL : 0>(src, radius, grp, [&](float2 t, int du, int dv) {
                 const Real D = Real(t.x), dD = D - g.Dc;
                 const Real fdu = Real(du), fdv = Real(dv);
@@ -452,8 +453,19 @@ __device__ PixelFit<Real> fit_pixel(const FitDesc& d, const NSrc& nsrc, const Sr
                 const Real qz = fmaT(Real(0.5), sz2, tz);
                 const Real ap = fmaT(Ah, sx, Bh * sy), cp = fmaT(Bh, sx, Ch * sy);
                 const Real e = fmaT(ap, sx, fmaT(cp, sy, -qz));
-                se += present(t) ? Acc(e * e) : Acc(0);
-                if constexpr (sizeof(Real) == 4) zmag = fmax(zmag, present(t) ? fabs(a2 * D) + fabs(b2) : Real(0));
+                if constexpr (sizeof(Real) == 4) {
+                    rse = fmaT(e, present(t) ? e : Real(0), rse);
+                    zmag = fmax(zmag, present(t) ? fabs(a2 * D) + fabs(b2) : Real(0));
+                } else {
+                    se += present(t) ? Acc(e * e) : Acc(0);
+                }
+            }, [&]() {
+                // FP32: the sum of each pair of rows in FP32, the pairs in FP64 (as the
+                // normal-equation sums below)
+                if constexpr (sizeof(Real) == 4) {
+                    se += Acc(rse);
+                    rse = 0;
+                }
             });
             se = grp.sum(se);
             const Acc mse = se / Acc(nfit);
