@@ -54,7 +54,8 @@ typedef enum { QC_DEPTH_U16 = 0, QC_DEPTH_F16 = 1, QC_DEPTH_F32 = 2 } qc_depth_f
 /* Arithmetic of the fit.
  *   MIXED: FP32 fit of every pixel; pixels whose equilibrated normal equations are
  *          ill-conditioned or whose last update is large are recomputed entirely in
- *          FP64 on the GPU (same input, same steps).
+ *          FP64 on the GPU (same input, same steps).  At radius 1 (a 3x3 window: nine
+ *          samples for six parameters) every pixel is fitted in FP64, as in FP64 mode.
  *   FP32:  FP32 only (flags still mark the pixels MIXED would recompute).
  *   FP64:  FP64 for every pixel. */
 typedef enum { QC_PREC_MIXED = 0, QC_PREC_FP32 = 1, QC_PREC_FP64 = 2 } qc_precision;

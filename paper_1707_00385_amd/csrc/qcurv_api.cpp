@@ -177,7 +177,11 @@ int tile_width_for(const qc_context* ctx, const qc_frame* f, const qc_params* p)
 // qc_tune recorded for its key (FP64 throughout where that measured faster); any other
 // request runs as asked.
 int32_t precision_for(const qc_context* ctx, const qc_frame* f, const qc_params* p) {
-    if (p->precision != QC_PREC_MIXED || p->tile_width != 0) return p->precision;
+    if (p->precision != QC_PREC_MIXED) return p->precision;
+    // A 3x3 window (nine samples for six parameters) leaves the FP32 fit too close to
+    // interpolation for the recompute criteria to bound its error: MIXED runs it in FP64.
+    if (p->radius == 1) return QC_PREC_FP64;
+    if (p->tile_width != 0) return p->precision;
     auto it = ctx->tuned.find(tune_key(f, p));
     return it != ctx->tuned.end() ? it->second.schedule : QC_PREC_MIXED;
 }

@@ -256,7 +256,7 @@ def test_batches_needing_more_lds_recapture():
         for i, cam in enumerate(cams):
             sc = scenes.cluttered_scene(cam, seed_frame=60 + i, config_index=3)
             frames.append((cam, upload_depth(sc.depth_u16(), "u16")))
-        for step, (r, tw) in enumerate(((2, 16), (18, 64), (3, 8), (18, 64), (1, 32))):
+        for step, (r, tw) in enumerate(((2, 16), (18, 64), (3, 8), (18, 64), (2, 32))):
             bj = []
             for cam, t in frames:
                 p = make_params(radius=r, iterations=3, tile_width=tw)

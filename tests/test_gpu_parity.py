@@ -95,6 +95,22 @@ def test_vga_noiseless_near_singular_initial_normal(ctx):
     _run(ctx, "vga f32 noiseless seed 20", sc.depth_m, "f32", sc.camera, 7, 5, 1e-4, scene=sc)
 
 
+def test_mixed_at_radius_one_is_fp64(ctx):
+    """A 3x3 window (nine samples for six parameters) is fitted in FP64 throughout in MIXED
+    (an FP32 fit of this noiseless frame left four pixels just beyond the tolerance that no
+    recompute criterion caught): MIXED gives FP64 mode's outputs bit for bit, every valid
+    pixel flagged FP64.  (Against the oracle the frame's last column, where a window holds
+    as many samples as parameters and the fit interpolates, has no determined answer.)"""
+    sc = scenes.cluttered_scene(scenes.CAM_VGA, seed_frame=30, config_index=1, noise=False, dropout=0.0)
+    log("[case] vga f32 noiseless r=1 T=3: mixed against fp64 mode")
+    gm = gpu_fit(ctx, sc.depth_m, "f32", sc.camera, radius=1, iterations=3, precision="mixed")
+    gf = gpu_fit(ctx, sc.depth_m, "f32", sc.camera, radius=1, iterations=3, precision="fp64")
+    for k in ("k1", "k2", "normal", "residual", "flags"):
+        assert np.array_equal(gm[k], gf[k], equal_nan=True), k
+    v = (gm["flags"] & 1) != 0
+    assert v.mean() > 0.9 and np.all((gm["flags"][v] & 2) != 0)
+
+
 @pytest.mark.parametrize("kind", ["tof", "hd"])
 def test_sensor_frames_whose_fit_moved_late(ctx, kind):
     """Noisy ToF and 720p frames, every pixel: each holds a pixel whose fit moved 0.2-0.6
